@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the spline hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+build (validate, rows, parallel Thomas solve for y'') and evaluate (uniform
+queries, bracketing, newint) for every curve of the workload.  The metric is
+instance-steps per second, where a step of a curve is one knot update or one
+query evaluation, so a pass over a curve with n knots and m queries is n + m
+steps.  Inputs are resident in HBM before the timed region starts.
+
+Workloads (--workload):
+  plain    (default) 1 curve, n = 13,000 knots, m = 2,048,000 uniform queries
+           (the paper's 13-knot / 2048-point worked size scaled 1000x), seed 0
+  small    1 curve, n = 13, m = 2048 (the worked size itself)
+  plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
+  batched  4096 curves, sizes log-uniform 0.1x..10x of the worked size, one
+           persistent fused launch (hipGraph replay), autotuned tiles
+  mixed    the batched workload with the FP32 solve + FP64 refinement
+  served   Poisson arrivals at 2000 req/s (sizes 0.1x..100x) through the
+           request API, continuous batching vs the plain one-request path
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "instances·steps/sec + HBM GB/s %peak; p50/p99 latency (served vs plain)"
+UNIT = "instance-steps/s"
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2001_09253_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get("%s|%s" % (kernel, workload))
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_cores_used(n):
+    return int(n)
+
+
+def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
+    import numpy as np
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    inst = workloads.single(0, n, m, bc=0)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(inst.x).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    ypp = torch.empty_like(x)
+    yq = torch.empty(m, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        api.spline_build(x, y, inst.start_deriv, inst.end_deriv, ypp)
+        api.spline_eval_uniform(x, y, ypp, m, yq)
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        api.spline_build(x, y, inst.start_deriv, inst.end_deriv, ypp)
+        ev[k][1].record(stream)
+        api.spline_eval_uniform(x, y, ypp, m, yq)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    eval_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    step_s = (t1 - t0) / K
+    value = (n + m) / step_s
+    # algorithmic bytes per launch: build reads x, y and writes y'' (24 n);
+    # evaluate reads x, y, y'' (24 n) and writes the m results (8 m)
+    kernels = {
+        "build": (build_ms, 24.0 * n),
+        "eval_uniform": (eval_ms, 24.0 * n + 8.0 * m),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dms, dbytes = kernels[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload_name, "instances": 1, "n": n, "m": m, "ends": "natural",
+                   "seed": 0, "generator": "x_j = x_{j-1} + U(0,1) (0 -> 1e-4), y_j = U(0,1)"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, workload_name),
+                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": dms},
+        "kernels_ms": {"build": build_ms, "eval_uniform": eval_ms},
+        "points_per_s": m / step_s, "knots_per_s": n / step_s,
+        "path_gbs": (24.0 * n + 8.0 * m + 24.0 * n) / step_s / 1e9,
+    }
+    out["path_frac_peak"] = out["path_gbs"] / HBM_PEAK_GBS
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_single(inst, args.cpu_seconds)
+    return out
+
+
+def cpu_baseline_single(inst, seconds):
+    import oracle
+    import numpy as np
+
+    n, m = inst.n, inst.m
+    # one warm call, then whole-workload repetitions for about `seconds`
+    oracle.spline_uniform(inst.x, inst.y, inst.start_deriv, inst.end_deriv, m)
+    reps = 0
+    t0 = oracle.now()
+    while True:
+        oracle.spline_uniform(inst.x, inst.y, inst.start_deriv, inst.end_deriv, m)
+        reps += 1
+        t = oracle.now() - t0
+        if t >= seconds:
+            break
+    per = t / reps
+    return {"value": (n + m) / per, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": "whole workload (n=%d, m=%d) repeated %d times in %.1f s, single thread" % (n, m, reps, t),
+            "ns_per_point": per / m * 1e9}
+
+
+def bench_batched(args, precision):
+    import numpy as np
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    b = workloads.batch(seed=0)
+    bufs = {"x": torch.from_numpy(b.x).cuda(), "y": torch.from_numpy(b.y).cuda(),
+            "sd": torch.from_numpy(b.sd).cuda(), "ed": torch.from_numpy(b.ed).cuda(),
+            "koff": torch.from_numpy(b.koff).cuda(), "qoff": torch.from_numpy(b.qoff).cuda(),
+            "yq": torch.empty(int(b.qoff[-1]), dtype=torch.float64, device="cuda"),
+            "ypp": torch.empty(int(b.koff[-1]), dtype=torch.float64, device="cuda")}
+    plan = api.spline_plan_create(b.koff, b.qoff, precision=precision)
+    cache = os.path.join(ROOT, "paper_2001_09253_amd", "autotune.json")
+    best, best_ms = api.spline_plan_autotune(plan, bufs, reps=5, cache_path=cache)
+    stream = torch.cuda.Stream()
+    api.spline_plan_capture(plan, bufs, stream=stream)
+    for _ in range(args.warmup):
+        api.spline_plan_replay(plan, stream=stream)
+    stream.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(K)]
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        api.spline_plan_replay(plan, stream=stream)
+        ev[k][1].record(stream)
+    stream.synchronize()
+    t1 = time.perf_counter()
+    launch_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    step_s = (t1 - t0) / K
+    N, M = int(b.koff[-1]), int(b.qoff[-1])
+    value = (N + M) / step_s
+    dbytes = 24.0 * N + 8.0 * M + 16.0 * b.count * 2 + 8.0 * b.count * 2
+    achieved = dbytes / (launch_ms * 1e-3) / 1e9
+    wl = "batched" if precision == api.FP64 else "mixed"
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == api.FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": wl, "instances": b.count, "sum_n": N, "sum_m": M,
+                   "sizes": "log-uniform 0.1x..10x of (13, 2048)", "ends": "natural/flat/twist cycle", "seed": 0,
+                   "tuning": {"block": best.block, "queries_per_tile": best.queries_per_tile,
+                              "grid_per_cu": best.grid_per_cu, "fused": best.fused}},
+        "roofline": {"bound": "hbm", "kernel": "fused_batch" if best.fused else "build+eval",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("fused_batch", wl),
+                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": launch_ms},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = 512
+        koff = b.koff[:sub + 1]
+        qoff = b.qoff[:sub + 1]
+        t0 = oracle.now()
+        reps = 0
+        used = 1
+        while True:
+            _, _, _, used = oracle.batch_uniform(koff, qoff, b.x[:koff[-1]], b.y[:koff[-1]], b.sd[:sub], b.ed[:sub])
+            reps += 1
+            if oracle.now() - t0 >= args.cpu_seconds:
+                break
+        t = oracle.now() - t0
+        steps = (int(koff[-1]) + int(qoff[-1])) * reps
+        out["cpu_baseline"] = {"value": steps / t, "unit": UNIT, "cores": used, "kind": "oracle",
+                               "sample": "first %d of the 4096 curves, %d repetitions in %.1f s, OpenMP over curves"
+                                         % (sub, reps, t)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "small", "plain2x", "batched", "mixed", "served"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: the spline path is measured on one MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "plain":
+        out = bench_single(args, 13000, 2048000, "plain: 1 curve, n=13000, m=2048000 uniform queries")
+    elif args.workload == "small":
+        out = bench_single(args, 13, 2048, "small: 1 curve, n=13, m=2048 uniform queries")
+    elif args.workload == "plain2x":
+        out = bench_single(args, 13000, 1 << 27, "plain2x: 1 curve, n=13000, m=2^27 uniform queries")
+    elif args.workload in ("batched", "mixed"):
+        from paper_2001_09253_amd import api
+        out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)
+    else:
+        from bench_serving import bench_served
+        out = bench_served(args)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * spline_solve.h -- C ABI of the MI355X (gfx950) cubic-spline library.
+ *
+ * The library implements the hot path of Hornbeck, "Fast Cubic Spline
+ * Interpolation" (arXiv 2001.09253) on the GPU, in FP64:
+ *
+ *   build    the knot second derivatives y''[n]: the tridiagonal system of the
+ *            section "Generating Second Derivatives" (equation eqn:init_val and
+ *            the rows a_j, b_j, c_j, d_j after it), with the end rows of the
+ *            section "Start and End Derivatives", solved by a parallel form of
+ *            Thomas' algorithm (section "Implementation");
+ *   evaluate m uniformly spaced queries between the first and the last knot
+ *            (section "Curve Interpolation", step 8 of the methodology), each
+ *            bracketed to its interval and evaluated with the rewritten
+ *            interpolant of the section "Fast Interpolation" (the routine the
+ *            paper calls newint).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Knots x[n] and values y[n] are FP64, contiguous, x strictly increasing,
+ *    n >= 3 (the paper's routine asserts both).  A NaN knot counts as not
+ *    increasing.
+ *  - An end is natural (y'' = 0 there) iff its derivative argument is
+ *    > 0.99e30, the paper's sentinel; otherwise it is clamped to that first
+ *    derivative.  Each end is decided on its own.  NaN values or derivatives
+ *    are not rejected: they propagate as NaN.
+ *  - Uniform query k of m is x[0] + k*h with h = (x[n-1]-x[0])/(m-1), one
+ *    multiply then one add (never fused), and query m-1 is x[n-1] itself;
+ *    with m == 1 the only query is x[0].
+ *  - The interval of query q is clip(#{j : x_j < q} - 1, 0, n-2): at an
+ *    interior knot the left interval, as the paper's bracketing loop picks.
+ *    Explicit queries outside [x[0], x[n-1]] use the end intervals (cubic
+ *    extrapolation).
+ *  - Return values: SOLVE_OK (0) or a negative SOLVE_E_* code.  No entry
+ *    point aborts the process.
+ *  - "device pointer" means memory the GPU can read or write (hipMalloc,
+ *    torch CUDA tensors); "stream" is a hipStream_t passed as void* (NULL =
+ *    the legacy default stream).  The device-level calls are asynchronous on
+ *    that stream and never allocate device memory.
+ */
+#ifndef SPLINE_SOLVE_H
+#define SPLINE_SOLVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------- */
+#define SOLVE_OK 0
+#define SOLVE_E_ARG (-1)     /* null pointer, bad config or option            */
+#define SOLVE_E_SIZE (-2)    /* n < 3, m < 1, or sizes beyond the limits      */
+#define SOLVE_E_ORDER (-3)   /* knots not strictly increasing (or NaN)        */
+#define SOLVE_E_BUDGET (-4)  /* one instance exceeds the whole HBM budget     */
+#define SOLVE_E_DEVICE (-5)  /* a HIP runtime call failed                     */
+#define SOLVE_E_TICKET (-6)  /* unknown or already reaped ticket              */
+#define SOLVE_E_STATE (-7)   /* context shutting down or in a failed state    */
+
+/* ---- request status (solve_poll) ------------------------------------------ */
+#define SOLVE_PENDING 0
+#define SOLVE_DONE 1
+#define SOLVE_ERROR 2
+
+/* ---- precision modes -------------------------------------------------------- */
+#define SOLVE_FP64 0          /* every step in FP64                              */
+#define SOLVE_FP32_REFINE 1   /* FP32 bulk solve + FP64 residual/correction      */
+
+/* ---- solve_config.flags ------------------------------------------------------ */
+#define SOLVE_PLAIN 1u        /* one instance per synchronous launch, no batching */
+#define SOLVE_NO_GRAPH 2u     /* launch kernels directly instead of a hipGraph    */
+
+/* ---- limits ------------------------------------------------------------------- */
+#define SOLVE_MAX_N_BLOCK 16384   /* largest n one workgroup solves (plain path) */
+#define SOLVE_MAX_N_BATCH 2048    /* largest n of an instance in a fused batch   */
+
+typedef struct solve_ctx solve_ctx;
+typedef uint64_t solve_ticket;
+
+typedef struct {
+    int device;                /* HIP device ordinal                                */
+    uint64_t hbm_budget_bytes; /* admission budget for resident request state       */
+    uint32_t max_slots;        /* max requests resident on the device at once       */
+    uint32_t precision;        /* SOLVE_FP64 or SOLVE_FP32_REFINE                    */
+    uint32_t flags;            /* SOLVE_PLAIN, SOLVE_NO_GRAPH                        */
+    uint32_t max_inflight;     /* batches in flight on the device (>= 1; 0 = 2)     */
+    void *stream;              /* optional hipStream_t for the compute work         */
+} solve_config;
+
+/* ============================================================================
+ * Request API (the method's problem statement: knots, values, start and end
+ * derivative as in the paper's routine new_second_derivative(knots, values,
+ * start_deriv, end_deriv), plus the points to interpolate at).
+ * ========================================================================== */
+
+/* Create a context on cfg->device.  *out receives an owned handle that must be
+ * released with solve_destroy.  A background scheduler thread admits
+ * requests against hbm_budget_bytes / max_slots and launches them in fused
+ * batches (continuous batching) unless SOLVE_PLAIN is set, in which case
+ * solve_submit runs the request synchronously.  Errors: E_ARG (null or bad
+ * config), E_DEVICE. */
+int solve_create(const solve_config *cfg, solve_ctx **out);
+
+/* Submit one curve.  knots/values: n doubles each (host or device pointers,
+ * detected per pointer); they are copied before the call returns, so the
+ * caller may free them at once.  start_deriv/end_deriv: see the conventions.
+ * xq: m explicit query points, or NULL for m uniform queries.  yq_out: m
+ * results, ypp_out: n second derivatives or NULL; both caller-owned, host or
+ * device, and written only when the request completes -- they must stay valid
+ * until solve_poll reports DONE/ERROR or until solve_destroy.  *ticket_out
+ * receives the request's ticket.  Errors: E_ARG, E_SIZE (n < 3, m < 1,
+ * n > SOLVE_MAX_N_BATCH without SOLVE_PLAIN, n > SOLVE_MAX_N_BLOCK), E_ORDER
+ * (the copied knots are checked before the call returns), E_BUDGET (the
+ * request's resident footprint 8*(3n + m [+ m for explicit queries]) + 64
+ * bytes exceeds hbm_budget_bytes), E_STATE (context shutting down),
+ * E_DEVICE.  With SOLVE_PLAIN the request has completed when the call
+ * returns (its ticket then polls DONE or ERROR). */
+int solve_submit(solve_ctx *ctx, const double *knots, const double *values, int64_t n,
+                 double start_deriv, double end_deriv, const double *xq, int64_t m,
+                 double *yq_out, double *ypp_out, solve_ticket *ticket_out);
+
+/* Non-blocking status of a ticket: *status = SOLVE_PENDING, SOLVE_DONE or
+ * SOLVE_ERROR.  A ticket reported DONE or ERROR is reaped: a later poll of it
+ * returns E_TICKET.  Errors: E_ARG, E_TICKET. */
+int solve_poll(solve_ctx *ctx, solve_ticket ticket, int *status);
+
+/* Blocking form of solve_poll: waits until the ticket is DONE or ERROR (or
+ * timeout_ms elapses, < 0 = forever; then *status = SOLVE_PENDING). */
+int solve_wait(solve_ctx *ctx, solve_ticket ticket, int *status, int64_t timeout_ms);
+
+/* Times of a completed or pending ticket in seconds on the library's
+ * monotonic clock (solve_clock): t[0] submit, t[1] admitted, t[2] launched,
+ * t[3] completed (0 where not reached yet); *error_code receives the ticket's
+ * own code (SOLVE_OK or E_ORDER).  Does not reap the ticket. */
+int solve_ticket_info(solve_ctx *ctx, solve_ticket ticket, double t[4], int *error_code);
+
+/* Library monotonic clock in seconds (the clock solve_ticket_info uses). */
+double solve_clock(void);
+
+/* Counters of a context: out[0] requests submitted, [1] completed, [2]
+ * failed, [3] batches launched, [4] resident bytes now, [5] peak resident
+ * bytes, [6] requests waiting for admission now, [7] peak requests in one
+ * batch. */
+int solve_stats(solve_ctx *ctx, uint64_t out[8]);
+
+/* Force the next batch launch to fail (host-side fault injection for tests of
+ * the error path; no kernel runs for that batch).  Its tickets report ERROR. */
+int solve_inject_fault(solve_ctx *ctx);
+
+/* Stop the scheduler, cancel queued work (its tickets report ERROR), wait for
+ * work already on the device, and free every device and host resource of the
+ * context.  Tickets of a destroyed context are unknown (E_TICKET). */
+int solve_destroy(solve_ctx *ctx);
+
+/* ============================================================================
+ * Device-level operations: one instance, device pointers, asynchronous on
+ * `stream`, no allocation.  These are the kernels the request API uses.
+ * ========================================================================== */
+
+/* Steps a1-a4: validate the knots, set up the rows, solve for y''.
+ * x, y: n device doubles; ypp: n device doubles (output).  status: nullable
+ * device int32, set to SOLVE_OK or SOLVE_E_ORDER (then ypp is all NaN).
+ * Host-side errors: E_ARG, E_SIZE (n < 3 or n > SOLVE_MAX_N_BLOCK). */
+int spline_build(const double *x, const double *y, int64_t n, double start_deriv,
+                 double end_deriv, double *ypp, int32_t *status, void *stream);
+
+/* Steps a5-a6: m uniform queries, bracketed and evaluated.  x, y, ypp: n
+ * device doubles (ypp from spline_build); yq: m device doubles (output).
+ * Errors: E_ARG, E_SIZE (n < 3 or m < 1). */
+int spline_eval_uniform(const double *x, const double *y, const double *ypp, int64_t n,
+                        int64_t m, double *yq, void *stream);
+
+/* Step a5 alone: the interval index of each of the m uniform queries
+ * (int32, device, output), computed by the same code as spline_eval_uniform. */
+int spline_bracket_uniform(const double *x, int64_t n, int64_t m, int32_t *idx, void *stream);
+
+/* The paper's "noop" loop on the GPU: generate and bracket the m uniform
+ * queries but store the interval index (as a double) instead of evaluating. */
+int spline_noop_uniform(const double *x, int64_t n, int64_t m, double *out, void *stream);
+
+/* Explicit queries (any order): xq[m] device doubles in; yq[m] values out;
+ * d1/d2 nullable outputs of the first and second derivative at the queries;
+ * idx nullable int32 output of the intervals. */
+int spline_eval_points(const double *x, const double *y, const double *ypp, int64_t n,
+                       const double *xq, int64_t m, double *yq, double *d1, double *d2,
+                       int32_t *idx, void *stream);
+
+/* ============================================================================
+ * Batched form: many curves in CSR layout in one persistent fused launch.
+ * ========================================================================== */
+
+typedef struct spline_plan spline_plan;
+
+/* Tuning knobs of a plan (0 = library default / autotuned choice). */
+typedef struct {
+    int32_t block;            /* threads per workgroup of the fused kernel: 256 or 512  */
+    int32_t queries_per_tile; /* uniform queries per evaluate tile (block * 1..16)       */
+    int32_t grid_per_cu;      /* persistent workgroups per compute unit (1..8)           */
+    int32_t fused;            /* 1: one persistent launch; 0: build + evaluate launches  */
+} spline_tuning;
+
+/* Plan a batch from host-side sizes: count instances, knot offsets koff[count+1]
+ * and query offsets qoff[count+1] (host int64, CSR: instance i owns knots
+ * koff[i]..koff[i+1]-1 and outputs qoff[i]..qoff[i+1]-1).  Every n_i must be
+ * in [3, SOLVE_MAX_N_BATCH] and every m_i >= 1.  precision: SOLVE_FP64 or
+ * SOLVE_FP32_REFINE.  tuning: nullable (library defaults).  The plan owns a
+ * device copy of the work table and scratch counters; *out must be released
+ * with spline_plan_destroy.  Errors: E_ARG, E_SIZE, E_DEVICE. */
+int spline_plan_create(int device, int64_t count, const int64_t *koff, const int64_t *qoff,
+                       uint32_t precision, const spline_tuning *tuning, spline_plan **out);
+
+/* Run the plan once on device-resident data: x, y (sum n doubles), sd, ed
+ * (count doubles), koff, qoff (count+1 int64, the same offsets as planned),
+ * yq (sum m doubles, output), ypp (sum n doubles, output, required: it holds
+ * the second derivatives the evaluation reads), status (nullable, count
+ * int32: SOLVE_OK or SOLVE_E_ORDER per instance).  Uniform queries only.
+ * Asynchronous on `stream`.  Two runs of one plan must not overlap. */
+int spline_plan_run(spline_plan *plan, const double *x, const double *y, const double *sd,
+                    const double *ed, const int64_t *koff, const int64_t *qoff, double *yq,
+                    double *ypp, int32_t *status, void *stream);
+
+/* Capture one spline_plan_run with these pointers into a hipGraph owned by
+ * the plan; spline_plan_replay then launches that graph on `stream`. */
+int spline_plan_capture(spline_plan *plan, const double *x, const double *y, const double *sd,
+                        const double *ed, const int64_t *koff, const int64_t *qoff, double *yq,
+                        double *ypp, int32_t *status, void *stream);
+int spline_plan_replay(spline_plan *plan, void *stream);
+
+/* Time candidate tunings of the plan on the given data (reps timed launches
+ * each), keep the fastest, and record it under `cache_path` (JSON, nullable)
+ * keyed by device architecture and size class.  *best receives the choice,
+ * *best_ms its mean launch time.  Outputs are overwritten while tuning. */
+int spline_plan_autotune(spline_plan *plan, const double *x, const double *y, const double *sd,
+                         const double *ed, const int64_t *koff, const int64_t *qoff, double *yq,
+                         double *ypp, int reps, const char *cache_path, spline_tuning *best,
+                         double *best_ms);
+
+/* The tuning a plan uses now. */
+int spline_plan_get_tuning(const spline_plan *plan, spline_tuning *out);
+
+int spline_plan_destroy(spline_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLINE_SOLVE_H */

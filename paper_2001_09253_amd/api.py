@@ -1,0 +1,260 @@
+"""Thin Python binding of the C ABI in include/spline_solve.h.
+
+Each function has the name of the C entry point it calls and only marshals
+arguments (tensor/array -> pointer, size checks, error code -> exception);
+every step of the spline path runs in the HIP library.  Device arguments are
+torch CUDA tensors (float64 / int32 / int64, contiguous); host arguments of the
+request API may be NumPy arrays or CPU tensors.  ``stream`` defaults to torch's
+current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _native
+from ._native import SolveConfig, Tuning
+
+OK, E_ARG, E_SIZE, E_ORDER, E_BUDGET, E_DEVICE, E_TICKET, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+PENDING, DONE, ERROR = 0, 1, 2
+FP64, FP32_REFINE = 0, 1
+PLAIN, NO_GRAPH = 1, 2
+MAX_N_BLOCK = 16384
+MAX_N_BATCH = 2048
+
+_NAMES = {OK: "OK", E_ARG: "E_ARG", E_SIZE: "E_SIZE", E_ORDER: "E_ORDER", E_BUDGET: "E_BUDGET",
+          E_DEVICE: "E_DEVICE", E_TICKET: "E_TICKET", E_STATE: "E_STATE"}
+
+
+class SolveError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        super().__init__("%s failed: %s (%d)" % (what, _NAMES.get(code, "?"), code))
+        self.code = code
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise SolveError(rc, what)
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dev(t, dtype=torch.float64, name="tensor", numel=None, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s needs at least %d elements" % (name, numel))
+    return C.c_void_p(t.data_ptr())
+
+
+def _any(a, name="array", optional=False):
+    """Pointer of a host array/tensor or a device tensor (request API)."""
+    if a is None:
+        if optional:
+            return None
+        raise ValueError("%s is required" % name)
+    if isinstance(a, torch.Tensor):
+        if not a.is_contiguous() or a.dtype != torch.float64:
+            raise TypeError("%s must be a contiguous float64 tensor" % name)
+        return C.c_void_p(a.data_ptr())
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise TypeError("%s must be a C-contiguous float64 array" % name)
+        return C.c_void_p(a.ctypes.data)
+    raise TypeError("%s must be a NumPy array or a torch tensor" % name)
+
+
+# -- device-level operations -------------------------------------------------------------
+
+def spline_build(x, y, start_deriv, end_deriv, ypp, status=None, stream=None):
+    n = x.numel()
+    _check(_native.lib().spline_build(_dev(x, name="x"), _dev(y, name="y", numel=n), n, float(start_deriv),
+                                      float(end_deriv), _dev(ypp, name="ypp", numel=n),
+                                      _dev(status, torch.int32, "status", 1, optional=True), _stream(stream)),
+           "spline_build")
+
+
+def spline_eval_uniform(x, y, ypp, m, yq, stream=None):
+    n = x.numel()
+    _check(_native.lib().spline_eval_uniform(_dev(x, name="x"), _dev(y, name="y", numel=n),
+                                             _dev(ypp, name="ypp", numel=n), n, int(m),
+                                             _dev(yq, name="yq", numel=int(m)), _stream(stream)),
+           "spline_eval_uniform")
+
+
+def spline_bracket_uniform(x, m, idx, stream=None):
+    _check(_native.lib().spline_bracket_uniform(_dev(x, name="x"), x.numel(), int(m),
+                                                _dev(idx, torch.int32, "idx", int(m)), _stream(stream)),
+           "spline_bracket_uniform")
+
+
+def spline_noop_uniform(x, m, out, stream=None):
+    _check(_native.lib().spline_noop_uniform(_dev(x, name="x"), x.numel(), int(m),
+                                             _dev(out, name="out", numel=int(m)), _stream(stream)),
+           "spline_noop_uniform")
+
+
+def spline_eval_points(x, y, ypp, xq, yq, d1=None, d2=None, idx=None, stream=None):
+    n, m = x.numel(), xq.numel()
+    _check(_native.lib().spline_eval_points(_dev(x, name="x"), _dev(y, name="y", numel=n),
+                                            _dev(ypp, name="ypp", numel=n), n, _dev(xq, name="xq"), m,
+                                            _dev(yq, name="yq", numel=m), _dev(d1, name="d1", numel=m, optional=True),
+                                            _dev(d2, name="d2", numel=m, optional=True),
+                                            _dev(idx, torch.int32, "idx", m, optional=True), _stream(stream)),
+           "spline_eval_points")
+
+
+# -- batched plans --------------------------------------------------------------------------
+
+class Plan:
+    """Owning wrapper of a spline_plan handle."""
+
+    def __init__(self, handle, count, koff, qoff):
+        self.handle = handle
+        self.count = count
+        self.koff = koff
+        self.qoff = qoff
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _native.lib().spline_plan_destroy(self.handle)
+            self.handle = None
+
+
+def spline_plan_create(koff, qoff, precision=FP64, tuning=None, device=None):
+    koff = np.ascontiguousarray(koff, dtype=np.int64)
+    qoff = np.ascontiguousarray(qoff, dtype=np.int64)
+    count = len(koff) - 1
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = C.c_void_p()
+    t = C.byref(tuning) if tuning is not None else None
+    _check(_native.lib().spline_plan_create(dev, count, koff.ctypes.data_as(C.c_void_p),
+                                            qoff.ctypes.data_as(C.c_void_p), int(precision), t, C.byref(h)),
+           "spline_plan_create")
+    return Plan(h, count, koff, qoff)
+
+
+def _plan_args(plan, b):
+    n_tot, m_tot = int(plan.koff[-1]), int(plan.qoff[-1])
+    return [_dev(b["x"], name="x", numel=n_tot), _dev(b["y"], name="y", numel=n_tot),
+            _dev(b["sd"], name="sd", numel=plan.count), _dev(b["ed"], name="ed", numel=plan.count),
+            _dev(b["koff"], torch.int64, "koff", plan.count + 1), _dev(b["qoff"], torch.int64, "qoff", plan.count + 1),
+            _dev(b["yq"], name="yq", numel=m_tot), _dev(b["ypp"], name="ypp", numel=n_tot)]
+
+
+def spline_plan_run(plan, bufs, status=None, stream=None):
+    """bufs: dict of device tensors x, y, sd, ed, koff, qoff, yq, ypp."""
+    _check(_native.lib().spline_plan_run(plan.handle, *_plan_args(plan, bufs),
+                                         _dev(status, torch.int32, "status", plan.count, optional=True),
+                                         _stream(stream)), "spline_plan_run")
+
+
+def spline_plan_capture(plan, bufs, status=None, stream=None):
+    _check(_native.lib().spline_plan_capture(plan.handle, *_plan_args(plan, bufs),
+                                             _dev(status, torch.int32, "status", plan.count, optional=True),
+                                             _stream(stream)), "spline_plan_capture")
+
+
+def spline_plan_replay(plan, stream=None):
+    _check(_native.lib().spline_plan_replay(plan.handle, _stream(stream)), "spline_plan_replay")
+
+
+def spline_plan_autotune(plan, bufs, reps=10, cache_path=None):
+    best = Tuning()
+    ms = C.c_double()
+    _check(_native.lib().spline_plan_autotune(plan.handle, *_plan_args(plan, bufs), int(reps),
+                                              cache_path.encode() if cache_path else None, C.byref(best),
+                                              C.byref(ms)), "spline_plan_autotune")
+    return best, ms.value
+
+
+def spline_plan_get_tuning(plan):
+    t = Tuning()
+    _check(_native.lib().spline_plan_get_tuning(plan.handle, C.byref(t)), "spline_plan_get_tuning")
+    return t
+
+
+# -- request API ------------------------------------------------------------------------------
+
+def solve_create(device=0, hbm_budget_bytes=200 << 30, max_slots=65536, precision=FP64, flags=0,
+                 max_inflight=2, stream=None):
+    cfg = SolveConfig(int(device), int(hbm_budget_bytes), int(max_slots), int(precision), int(flags),
+                      int(max_inflight), None if stream is None else _stream(stream))
+    h = C.c_void_p()
+    _check(_native.lib().solve_create(C.byref(cfg), C.byref(h)), "solve_create")
+    return h
+
+
+def solve_submit(ctx, knots, values, start_deriv, end_deriv, xq, m, yq_out, ypp_out=None):
+    """Returns the ticket.  yq_out / ypp_out must stay alive until the ticket is
+    reported DONE or ERROR."""
+    n = int(len(knots))
+    if len(values) != n:
+        raise SolveError(E_SIZE, "solve_submit")
+    t = C.c_uint64()
+    _check(_native.lib().solve_submit(ctx, _any(knots, "knots"), _any(values, "values"), n, float(start_deriv),
+                                      float(end_deriv), _any(xq, "xq", optional=True), int(m),
+                                      _any(yq_out, "yq_out"), _any(ypp_out, "ypp_out", optional=True),
+                                      C.byref(t)), "solve_submit")
+    return t.value
+
+
+def solve_poll(ctx, ticket):
+    st = C.c_int()
+    _check(_native.lib().solve_poll(ctx, int(ticket), C.byref(st)), "solve_poll")
+    return st.value
+
+
+def solve_wait(ctx, ticket, timeout_ms=-1):
+    st = C.c_int()
+    _check(_native.lib().solve_wait(ctx, int(ticket), C.byref(st), int(timeout_ms)), "solve_wait")
+    return st.value
+
+
+def solve_ticket_info(ctx, ticket):
+    t = (C.c_double * 4)()
+    code = C.c_int()
+    _check(_native.lib().solve_ticket_info(ctx, int(ticket), t, C.byref(code)), "solve_ticket_info")
+    return list(t), code.value
+
+
+def solve_clock():
+    return _native.lib().solve_clock()
+
+
+def solve_stats(ctx):
+    out = (C.c_uint64 * 8)()
+    _check(_native.lib().solve_stats(ctx, out), "solve_stats")
+    keys = ["submitted", "completed", "failed", "batches", "resident_bytes", "peak_resident_bytes",
+            "waiting", "peak_batch"]
+    return dict(zip(keys, list(out)))
+
+
+def solve_inject_fault(ctx):
+    _check(_native.lib().solve_inject_fault(ctx), "solve_inject_fault")
+
+
+def solve_destroy(ctx):
+    _check(_native.lib().solve_destroy(ctx), "solve_destroy")
+
+
+def spline_plan_destroy(plan):
+    """Release a plan (also done when the Plan object is collected)."""
+    plan.destroy()

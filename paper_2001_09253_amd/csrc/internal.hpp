@@ -1,0 +1,16 @@
+// Launch helpers shared between the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spl {
+
+int launch_build(const double* x, const double* y, int64_t n, double sd, double ed, double* ypp,
+                 int32_t* status, hipStream_t s);
+int launch_eval_uniform_values(const double* x, const double* y, const double* ypp, int64_t n, int64_t m,
+                               double* yq, hipStream_t s);
+int launch_eval_points(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
+                       int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s);
+
+}  // namespace spl

@@ -1,0 +1,696 @@
+// Request API of the C ABI (solve_create / submit / poll / wait / destroy):
+// HBM-budget admission, continuous batching over in-flight slots, and the
+// plain one-request-per-synchronous-launch mode.
+//
+// Life of a request (batched mode):
+//   submit   inputs copied to host memory owned by the request, validated
+//            (n, order, sizes), footprint priced, queued (FIFO);
+//   admit    the scheduler thread takes queued requests while the resident
+//            footprint stays within the budget and the slot count (a bounded
+//            look-ahead lets smaller requests pass a large head request,
+//            until the head has been passed over too often);
+//   launch   the admitted requests form one batch on a free in-flight slot:
+//            inputs staged in pinned memory, copied to HBM, one persistent
+//            fused launch builds and evaluates all of them (plus an explicit-
+//            query kernel per request that brings its own points), results
+//            copied back, an event recorded -- optionally as one hipGraph;
+//   done     when the event completes, results reach the caller's buffers,
+//            the footprint is released and the ticket turns DONE.
+// New requests are admitted while earlier batches are still on the device
+// (up to max_inflight batches overlap), which is continuous batching.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batch.hpp"
+#include "internal.hpp"
+#include "spline_solve.h"
+
+namespace {
+
+using spl::Batch;
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap && p) return SOLVE_OK;
+        const size_t want = std::max(bytes, cap + cap / 2) + 256;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return SOLVE_E_DEVICE;
+        }
+        cap = want;
+        return SOLVE_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+struct HostBuf {  // pinned host staging
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap && p) return SOLVE_OK;
+        const size_t want = std::max(bytes, cap + cap / 2) + 256;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return SOLVE_E_DEVICE;
+        }
+        cap = want;
+        return SOLVE_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the sticky error of an unknown host pointer
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+struct Req {
+    solve_ticket id = 0;
+    int64_t n = 0, m = 0;
+    double sd = 0, ed = 0;
+    std::vector<double> x, y, xq;  // owned copies of the inputs
+    double* yq_out = nullptr;
+    double* ypp_out = nullptr;
+    bool yq_dev = false, ypp_dev = false;
+    int status = SOLVE_PENDING;
+    int code = SOLVE_OK;
+    double t[4] = {0, 0, 0, 0};
+    uint64_t bytes = 0;
+    int passed_over = 0;
+    bool explicit_q() const { return !xq.empty(); }
+};
+using ReqP = std::shared_ptr<Req>;
+
+// Device footprint of one request while resident: knots, values, second
+// derivatives and results (plus its query points when explicit), and its
+// share of the work tables.
+uint64_t footprint(int64_t n, int64_t m, bool explicit_q) {
+    return 8ull * (uint64_t)(3 * n + m + (explicit_q ? m : 0)) + 64ull;
+}
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::unique_ptr<Batch> batch;
+    bool busy = false;
+    bool failed = false;
+    std::vector<ReqP> reqs;
+    uint64_t bytes = 0;
+    DevBuf x, y, ypp, yq, sd, ed, koff, qoff, xq, status;
+    HostBuf hx, hy, hypp, hyq, hsd, hed, hkoff, hqoff, hxq, hstatus, htab;
+    std::vector<uint8_t> uniform;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+}  // namespace
+
+struct solve_ctx {
+    solve_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_sched;
+    std::condition_variable cv_done;
+    std::deque<ReqP> queue;
+    std::unordered_map<solve_ticket, ReqP> tickets;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::thread sched;
+    bool stop = false;
+    bool inject = false;
+    bool failed_state = false;
+    uint64_t next_ticket = 1;
+    uint64_t resident = 0, peak_resident = 0, resident_reqs = 0;
+    uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_batches = 0, peak_batch = 0;
+    spline_tuning tuning = spl::default_tuning();
+    // plain mode
+    std::mutex plain_mu;
+    hipStream_t plain_stream = nullptr;
+    DevBuf px, py, pypp, pyq, pxq, pstatus;
+};
+
+namespace {
+
+struct DevCtx {
+    int prev = -1;
+    explicit DevCtx(int dev) {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevCtx() {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void finish_locked(solve_ctx* c, const ReqP& r, int status, int code) {
+    r->status = status;
+    r->code = code;
+    r->t[3] = now_s();
+    if (status == SOLVE_DONE) ++c->n_completed; else ++c->n_failed;
+}
+
+// Stage, copy and launch one batch on slot s (called without the lock; the
+// slot is owned by the scheduler thread until its event completes).
+int launch_batch(solve_ctx* c, Slot& s) {
+    const int64_t count = (int64_t)s.reqs.size();
+    int64_t nt = 0, mt = 0, xt = 0;
+    bool want_ypp = false;
+    for (const auto& r : s.reqs) {
+        nt += r->n;
+        mt += r->m;
+        if (r->explicit_q()) xt += r->m;
+        want_ypp |= r->ypp_out != nullptr;
+    }
+    int rc = SOLVE_OK;
+    rc = rc ? rc : s.hkoff.ensure(8 * (count + 1));
+    rc = rc ? rc : s.hqoff.ensure(8 * (count + 1));
+    rc = rc ? rc : s.hx.ensure(8 * nt);
+    rc = rc ? rc : s.hy.ensure(8 * nt);
+    rc = rc ? rc : s.hsd.ensure(8 * count);
+    rc = rc ? rc : s.hed.ensure(8 * count);
+    rc = rc ? rc : s.hyq.ensure(8 * mt);
+    rc = rc ? rc : s.hypp.ensure(8 * nt);
+    rc = rc ? rc : s.hstatus.ensure(4 * count);
+    rc = rc ? rc : s.hxq.ensure(8 * std::max<int64_t>(xt, 1));
+    if (rc) return rc;
+    int64_t* koff = s.hkoff.as<int64_t>();
+    int64_t* qoff = s.hqoff.as<int64_t>();
+    s.uniform.assign(count, 1);
+    koff[0] = 0;
+    qoff[0] = 0;
+    int64_t xo = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const Req& r = *s.reqs[i];
+        std::memcpy(s.hx.as<double>() + koff[i], r.x.data(), 8 * r.n);
+        std::memcpy(s.hy.as<double>() + koff[i], r.y.data(), 8 * r.n);
+        s.hsd.as<double>()[i] = r.sd;
+        s.hed.as<double>()[i] = r.ed;
+        if (r.explicit_q()) {
+            std::memcpy(s.hxq.as<double>() + xo, r.xq.data(), 8 * r.m);
+            xo += r.m;
+            s.uniform[i] = 0;
+        }
+        koff[i + 1] = koff[i] + r.n;
+        qoff[i + 1] = qoff[i] + r.m;
+    }
+    if (!s.batch) s.batch.reset(new Batch(c->cfg.device));
+    rc = s.batch->plan(count, koff, qoff, c->tuning, c->cfg.precision, s.uniform.data());
+    if (rc) return rc;
+    rc = rc ? rc : s.htab.ensure(std::max<size_t>(s.batch->table_bytes(), 64));
+    rc = rc ? rc : s.x.ensure(8 * nt);
+    rc = rc ? rc : s.y.ensure(8 * nt);
+    rc = rc ? rc : s.ypp.ensure(8 * nt);
+    rc = rc ? rc : s.yq.ensure(8 * mt);
+    rc = rc ? rc : s.sd.ensure(8 * count);
+    rc = rc ? rc : s.ed.ensure(8 * count);
+    rc = rc ? rc : s.koff.ensure(8 * (count + 1));
+    rc = rc ? rc : s.qoff.ensure(8 * (count + 1));
+    rc = rc ? rc : s.status.ensure(4 * count);
+    rc = rc ? rc : s.xq.ensure(8 * std::max<int64_t>(xt, 1));
+    if (rc) return rc;
+
+    const bool use_graph = !(c->cfg.flags & SOLVE_NO_GRAPH);
+    hipStream_t st = s.stream;
+    s.drop_graph();
+    if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SOLVE_E_DEVICE;
+    auto h2d = [&](DevBuf& d, const HostBuf& h, size_t b) {
+        if (!rc && b && hipMemcpyAsync(d.p, h.p, b, hipMemcpyHostToDevice, st) != hipSuccess) rc = SOLVE_E_DEVICE;
+    };
+    auto d2h = [&](HostBuf& h, const DevBuf& d, size_t b) {
+        if (!rc && b && hipMemcpyAsync(h.p, d.p, b, hipMemcpyDeviceToHost, st) != hipSuccess) rc = SOLVE_E_DEVICE;
+    };
+    rc = s.batch->upload_staged(st, s.htab.p);
+    h2d(s.x, s.hx, 8 * nt);
+    h2d(s.y, s.hy, 8 * nt);
+    h2d(s.sd, s.hsd, 8 * count);
+    h2d(s.ed, s.hed, 8 * count);
+    h2d(s.koff, s.hkoff, 8 * (count + 1));
+    h2d(s.qoff, s.hqoff, 8 * (count + 1));
+    if (xt) h2d(s.xq, s.hxq, 8 * xt);
+    if (!rc)
+        rc = s.batch->launch(s.x.as<double>(), s.y.as<double>(), s.sd.as<double>(), s.ed.as<double>(),
+                             s.koff.as<int64_t>(), s.qoff.as<int64_t>(), s.yq.as<double>(), s.ypp.as<double>(),
+                             s.status.as<int32_t>(), st);
+    xo = 0;
+    for (int64_t i = 0; i < count && !rc; ++i) {
+        const Req& r = *s.reqs[i];
+        if (!r.explicit_q()) continue;
+        rc = spl::launch_eval_points(s.x.as<double>() + koff[i], s.y.as<double>() + koff[i],
+                                     s.ypp.as<double>() + koff[i], r.n, s.xq.as<double>() + xo, r.m,
+                                     s.yq.as<double>() + qoff[i], nullptr, nullptr, nullptr, st);
+        xo += r.m;
+    }
+    // Results: device-resident callers get a device-to-device copy, host
+    // callers go through the pinned staging.
+    bool any_host_yq = false;
+    for (int64_t i = 0; i < count && !rc; ++i) {
+        const Req& r = *s.reqs[i];
+        if (r.yq_dev) {
+            if (hipMemcpyAsync(r.yq_out, s.yq.as<double>() + qoff[i], 8 * r.m, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                rc = SOLVE_E_DEVICE;
+        } else {
+            any_host_yq = true;
+        }
+        if (r.ypp_out && r.ypp_dev) {
+            if (hipMemcpyAsync(r.ypp_out, s.ypp.as<double>() + koff[i], 8 * r.n, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                rc = SOLVE_E_DEVICE;
+        }
+    }
+    if (any_host_yq) d2h(s.hyq, s.yq, 8 * mt);
+    if (want_ypp) d2h(s.hypp, s.ypp, 8 * nt);
+    d2h(s.hstatus, s.status, 4 * count);
+    if (use_graph) {
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (!rc && (e != hipSuccess || !g)) rc = SOLVE_E_DEVICE;
+        if (g && rc) (void)hipGraphDestroy(g);
+        if (!rc) {
+            s.graph = g;
+            if (hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0) != hipSuccess) {
+                s.exec = nullptr;
+                rc = SOLVE_E_DEVICE;
+            }
+        }
+        if (!rc && hipGraphLaunch(s.exec, st) != hipSuccess) rc = SOLVE_E_DEVICE;
+    }
+    if (!rc && hipEventRecord(s.done, st) != hipSuccess) rc = SOLVE_E_DEVICE;
+    return rc;
+}
+
+// Deliver the results of a completed slot (called without the lock).
+void deliver(Slot& s) {
+    const int64_t* koff = s.hkoff.as<int64_t>();
+    const int64_t* qoff = s.hqoff.as<int64_t>();
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+        Req& r = *s.reqs[i];
+        if (s.failed) continue;
+        r.code = s.hstatus.as<int32_t>()[i];
+        if (!r.yq_dev) std::memcpy(r.yq_out, s.hyq.as<double>() + qoff[i], 8 * r.m);
+        if (r.ypp_out && !r.ypp_dev) std::memcpy(r.ypp_out, s.hypp.as<double>() + koff[i], 8 * r.n);
+    }
+}
+
+// Requests for the next batch: FIFO within the budget and the slot limit,
+// with a bounded look-ahead past a head request that does not fit yet.
+std::vector<ReqP> admit_locked(solve_ctx* c) {
+    std::vector<ReqP> out;
+    const size_t window = 64;
+    const int64_t max_batch_queries = (int64_t)1 << 27;
+    uint64_t bytes = 0;
+    int64_t queries = 0;
+    size_t scanned = 0;
+    bool head_blocked = false;
+    for (auto it = c->queue.begin(); it != c->queue.end() && scanned < window;) {
+        ++scanned;
+        const ReqP& r = *it;
+        if (c->resident_reqs + out.size() + 1 > c->cfg.max_slots) break;
+        const bool fits = c->resident + bytes + r->bytes <= c->cfg.hbm_budget_bytes &&
+                          (out.empty() || queries + r->m <= max_batch_queries);
+        if (fits && !(head_blocked && c->queue.front()->passed_over > 8)) {
+            bytes += r->bytes;
+            queries += r->m;
+            out.push_back(r);
+            it = c->queue.erase(it);
+            continue;
+        }
+        if (!head_blocked) {
+            head_blocked = true;
+            ++r->passed_over;
+            if (r->passed_over > 8) break;  // let the resident set drain for it
+        }
+        ++it;
+    }
+    return out;
+}
+
+void scheduler(solve_ctx* c) {
+    (void)hipSetDevice(c->cfg.device);
+    std::unique_lock<std::mutex> lk(c->mu);
+    for (;;) {
+        // 1. retire completed batches
+        for (auto& sp : c->slots) {
+            Slot& s = *sp;
+            if (!s.busy) continue;
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) s.failed = true;
+            lk.unlock();
+            if (!s.failed && hipStreamSynchronize(s.stream) != hipSuccess) s.failed = true;
+            deliver(s);
+            s.drop_graph();
+            lk.lock();
+            for (auto& r : s.reqs) {
+                if (s.failed) finish_locked(c, r, SOLVE_ERROR, SOLVE_E_DEVICE);
+                else finish_locked(c, r, r->code == SOLVE_OK ? SOLVE_DONE : SOLVE_ERROR, r->code);
+            }
+            c->resident -= s.bytes;
+            c->resident_reqs -= s.reqs.size();
+            s.reqs.clear();
+            s.bytes = 0;
+            s.busy = false;
+            s.failed = false;
+            c->cv_done.notify_all();
+        }
+        // 2. cancel queued work on shutdown
+        if (c->stop && !c->queue.empty()) {
+            for (auto& r : c->queue) finish_locked(c, r, SOLVE_ERROR, SOLVE_E_STATE);
+            c->queue.clear();
+            c->cv_done.notify_all();
+        }
+        // 3. launch a new batch on a free slot
+        Slot* free_slot = nullptr;
+        bool any_busy = false;
+        for (auto& sp : c->slots) {
+            if (sp->busy) any_busy = true;
+            else if (!free_slot) free_slot = sp.get();
+        }
+        if (!c->stop && free_slot && !c->queue.empty()) {
+            std::vector<ReqP> reqs = admit_locked(c);
+            if (!reqs.empty()) {
+                Slot& s = *free_slot;
+                s.busy = true;
+                s.reqs = std::move(reqs);
+                s.bytes = 0;
+                const double ta = now_s();
+                for (auto& r : s.reqs) {
+                    s.bytes += r->bytes;
+                    r->t[1] = ta;
+                }
+                c->resident += s.bytes;
+                c->resident_reqs += s.reqs.size();
+                c->peak_resident = std::max(c->peak_resident, c->resident);
+                c->peak_batch = std::max<uint64_t>(c->peak_batch, s.reqs.size());
+                ++c->n_batches;
+                const bool fault = c->inject;
+                c->inject = false;
+                lk.unlock();
+                int rc = fault ? SOLVE_E_DEVICE : launch_batch(c, s);
+                const double tl = now_s();
+                lk.lock();
+                for (auto& r : s.reqs) r->t[2] = tl;
+                if (rc) {
+                    // nothing of this batch reached the device, or it failed to
+                    // launch: wait for whatever was queued, then fail its tickets
+                    lk.unlock();
+                    (void)hipStreamSynchronize(s.stream);
+                    (void)hipGetLastError();
+                    s.drop_graph();
+                    lk.lock();
+                    for (auto& r : s.reqs) finish_locked(c, r, SOLVE_ERROR, rc == SOLVE_E_ORDER ? rc : SOLVE_E_DEVICE);
+                    c->resident -= s.bytes;
+                    c->resident_reqs -= s.reqs.size();
+                    s.reqs.clear();
+                    s.bytes = 0;
+                    s.busy = false;
+                    c->cv_done.notify_all();
+                }
+                continue;
+            }
+        }
+        if (c->stop && c->queue.empty() && !any_busy) break;
+        if (any_busy) c->cv_sched.wait_for(lk, std::chrono::microseconds(20));
+        else c->cv_sched.wait(lk);
+    }
+}
+
+int copy_in(std::vector<double>& dst, const double* src, int64_t n) {
+    dst.resize((size_t)n);
+    if (is_device_ptr(src)) {
+        if (hipMemcpy(dst.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return SOLVE_E_DEVICE;
+    } else {
+        std::memcpy(dst.data(), src, 8 * (size_t)n);
+    }
+    return SOLVE_OK;
+}
+
+int run_plain(solve_ctx* c, Req& r) {
+    std::lock_guard<std::mutex> g(c->plain_mu);
+    hipStream_t s = c->plain_stream;
+    int rc = SOLVE_OK;
+    rc = rc ? rc : c->px.ensure(8 * r.n);
+    rc = rc ? rc : c->py.ensure(8 * r.n);
+    rc = rc ? rc : c->pypp.ensure(8 * r.n);
+    rc = rc ? rc : c->pyq.ensure(8 * r.m);
+    rc = rc ? rc : c->pstatus.ensure(4);
+    if (r.explicit_q()) rc = rc ? rc : c->pxq.ensure(8 * r.m);
+    if (rc) return rc;
+    r.t[1] = r.t[2] = now_s();
+    if (hipMemcpyAsync(c->px.p, r.x.data(), 8 * r.n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->py.p, r.y.data(), 8 * r.n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return SOLVE_E_DEVICE;
+    rc = spl::launch_build(c->px.as<double>(), c->py.as<double>(), r.n, r.sd, r.ed, c->pypp.as<double>(),
+                           c->pstatus.as<int32_t>(), s);
+    if (!rc) {
+        if (r.explicit_q()) {
+            if (hipMemcpyAsync(c->pxq.p, r.xq.data(), 8 * r.m, hipMemcpyHostToDevice, s) != hipSuccess)
+                return SOLVE_E_DEVICE;
+            rc = spl::launch_eval_points(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
+                                         c->pxq.as<double>(), r.m, c->pyq.as<double>(), nullptr, nullptr, nullptr, s);
+        } else {
+            rc = spl::launch_eval_uniform_values(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
+                                                 r.m, c->pyq.as<double>(), s);
+        }
+    }
+    if (rc) return rc;
+    const hipMemcpyKind kq = r.yq_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (hipMemcpyAsync(r.yq_out, c->pyq.p, 8 * r.m, kq, s) != hipSuccess) return SOLVE_E_DEVICE;
+    if (r.ypp_out) {
+        const hipMemcpyKind kp = r.ypp_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (hipMemcpyAsync(r.ypp_out, c->pypp.p, 8 * r.n, kp, s) != hipSuccess) return SOLVE_E_DEVICE;
+    }
+    int32_t st = 0;
+    if (hipMemcpyAsync(&st, c->pstatus.p, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return SOLVE_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return SOLVE_E_DEVICE;
+    return st == 0 ? SOLVE_OK : st;
+}
+
+}  // namespace
+
+extern "C" double solve_clock(void) { return now_s(); }
+
+extern "C" int solve_create(const solve_config* cfg, solve_ctx** out) {
+    if (!cfg || !out) return SOLVE_E_ARG;
+    *out = nullptr;
+    if (cfg->hbm_budget_bytes == 0 || cfg->max_slots == 0) return SOLVE_E_ARG;
+    if (cfg->precision != SOLVE_FP64 && cfg->precision != SOLVE_FP32_REFINE) return SOLVE_E_ARG;
+    if (cfg->flags & ~(SOLVE_PLAIN | SOLVE_NO_GRAPH)) return SOLVE_E_ARG;
+    if (cfg->max_inflight > 8) return SOLVE_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return SOLVE_E_DEVICE;
+    DevCtx g(cfg->device);
+    solve_ctx* c = new solve_ctx();
+    c->cfg = *cfg;
+    if (c->cfg.max_inflight == 0) c->cfg.max_inflight = 2;
+    if (hipStreamCreateWithFlags(&c->plain_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return SOLVE_E_DEVICE;
+    }
+    if (!(cfg->flags & SOLVE_PLAIN)) {
+        for (uint32_t i = 0; i < c->cfg.max_inflight; ++i) {
+            std::unique_ptr<Slot> s(new Slot());
+            if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+                if (s->stream) (void)hipStreamDestroy(s->stream);
+                for (auto& t : c->slots) {
+                    (void)hipStreamDestroy(t->stream);
+                    (void)hipEventDestroy(t->done);
+                }
+                (void)hipStreamDestroy(c->plain_stream);
+                delete c;
+                return SOLVE_E_DEVICE;
+            }
+            c->slots.push_back(std::move(s));
+        }
+        c->sched = std::thread(scheduler, c);
+    }
+    *out = c;
+    return SOLVE_OK;
+}
+
+extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* values, int64_t n, double start_deriv,
+                            double end_deriv, const double* xq, int64_t m, double* yq_out, double* ypp_out,
+                            solve_ticket* ticket_out) {
+    if (!c || !knots || !values || !yq_out || !ticket_out) return SOLVE_E_ARG;
+    const bool plain = (c->cfg.flags & SOLVE_PLAIN) != 0;
+    if (n < 3 || m < 1) return SOLVE_E_SIZE;
+    if (n > (plain ? SOLVE_MAX_N_BLOCK : SOLVE_MAX_N_BATCH)) return SOLVE_E_SIZE;
+    DevCtx g(c->cfg.device);
+    ReqP r = std::make_shared<Req>();
+    r->t[0] = now_s();
+    r->n = n;
+    r->m = m;
+    r->sd = start_deriv;
+    r->ed = end_deriv;
+    r->yq_out = yq_out;
+    r->ypp_out = ypp_out;
+    r->yq_dev = is_device_ptr(yq_out);
+    r->ypp_dev = ypp_out && is_device_ptr(ypp_out);
+    int rc = copy_in(r->x, knots, n);
+    if (!rc) rc = copy_in(r->y, values, n);
+    if (!rc && xq) rc = copy_in(r->xq, xq, m);
+    if (rc) return rc;
+    for (int64_t j = 1; j < n; ++j)
+        if (!(r->x[j] > r->x[j - 1])) return SOLVE_E_ORDER;
+    r->bytes = footprint(n, m, xq != nullptr);
+    if (r->bytes > c->cfg.hbm_budget_bytes) return SOLVE_E_BUDGET;
+    if (plain) {
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            if (c->stop) return SOLVE_E_STATE;
+            r->id = c->next_ticket++;
+            ++c->n_submitted;
+            c->tickets[r->id] = r;
+        }
+        const int prc = run_plain(c, *r);
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (prc == SOLVE_OK) finish_locked(c, r, SOLVE_DONE, SOLVE_OK);
+        else finish_locked(c, r, SOLVE_ERROR, prc);
+        *ticket_out = r->id;
+        c->cv_done.notify_all();
+        return SOLVE_OK;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->stop) return SOLVE_E_STATE;
+    r->id = c->next_ticket++;
+    ++c->n_submitted;
+    c->tickets[r->id] = r;
+    c->queue.push_back(r);
+    *ticket_out = r->id;
+    c->cv_sched.notify_one();
+    return SOLVE_OK;
+}
+
+extern "C" int solve_poll(solve_ctx* c, solve_ticket t, int* status) {
+    if (!c || !status) return SOLVE_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->tickets.find(t);
+    if (it == c->tickets.end()) return SOLVE_E_TICKET;
+    *status = it->second->status;
+    if (*status != SOLVE_PENDING) c->tickets.erase(it);
+    return SOLVE_OK;
+}
+
+extern "C" int solve_wait(solve_ctx* c, solve_ticket t, int* status, int64_t timeout_ms) {
+    if (!c || !status) return SOLVE_E_ARG;
+    std::unique_lock<std::mutex> lk(c->mu);
+    auto it = c->tickets.find(t);
+    if (it == c->tickets.end()) return SOLVE_E_TICKET;
+    ReqP r = it->second;
+    auto ready = [&] { return r->status != SOLVE_PENDING; };
+    if (timeout_ms < 0) c->cv_done.wait(lk, ready);
+    else c->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+    *status = r->status;
+    if (*status != SOLVE_PENDING) c->tickets.erase(t);
+    return SOLVE_OK;
+}
+
+extern "C" int solve_ticket_info(solve_ctx* c, solve_ticket t, double times[4], int* error_code) {
+    if (!c || !times) return SOLVE_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->tickets.find(t);
+    if (it == c->tickets.end()) return SOLVE_E_TICKET;
+    for (int i = 0; i < 4; ++i) times[i] = it->second->t[i];
+    if (error_code) *error_code = it->second->code;
+    return SOLVE_OK;
+}
+
+extern "C" int solve_stats(solve_ctx* c, uint64_t out[8]) {
+    if (!c || !out) return SOLVE_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    out[0] = c->n_submitted;
+    out[1] = c->n_completed;
+    out[2] = c->n_failed;
+    out[3] = c->n_batches;
+    out[4] = c->resident;
+    out[5] = c->peak_resident;
+    out[6] = c->queue.size();
+    out[7] = c->peak_batch;
+    return SOLVE_OK;
+}
+
+extern "C" int solve_inject_fault(solve_ctx* c) {
+    if (!c) return SOLVE_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->inject = true;
+    return SOLVE_OK;
+}
+
+extern "C" int solve_destroy(solve_ctx* c) {
+    if (!c) return SOLVE_E_ARG;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->stop = true;
+        c->cv_sched.notify_all();
+    }
+    if (c->sched.joinable()) c->sched.join();
+    DevCtx g(c->cfg.device);
+    {
+        std::lock_guard<std::mutex> pg(c->plain_mu);
+        (void)hipStreamSynchronize(c->plain_stream);
+    }
+    for (auto& s : c->slots) {
+        (void)hipStreamSynchronize(s->stream);
+        s->drop_graph();
+        s->batch.reset();
+        for (DevBuf* d : {&s->x, &s->y, &s->ypp, &s->yq, &s->sd, &s->ed, &s->koff, &s->qoff, &s->xq, &s->status})
+            d->release();
+        for (HostBuf* h : {&s->hx, &s->hy, &s->hypp, &s->hyq, &s->hsd, &s->hed, &s->hkoff, &s->hqoff, &s->hxq,
+                           &s->hstatus, &s->htab})
+            h->release();
+        (void)hipEventDestroy(s->done);
+        (void)hipStreamDestroy(s->stream);
+    }
+    for (DevBuf* d : {&c->px, &c->py, &c->pypp, &c->pyq, &c->pxq, &c->pstatus}) d->release();
+    (void)hipStreamDestroy(c->plain_stream);
+    delete c;
+    return SOLVE_OK;
+}

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/spline_solve.h declares, and rejects bad arguments
+before touching a device."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2001_09253_amd import _native, api
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _native.lib()
+
+
+def test_header_declares_the_request_api():
+    names = _native.header_functions()
+    for f in ("solve_create", "solve_submit", "solve_poll", "solve_destroy"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _native.header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), "missing export: %s" % name
+        assert name in _native.SIGNATURES, "binding has no signature for %s" % name
+
+
+def test_binding_covers_only_declared_functions():
+    assert set(_native.SIGNATURES) == set(_native.header_functions())
+
+
+def test_python_binding_names_match():
+    for name in _native.header_functions():
+        assert hasattr(api, name), "api lacks %s" % name
+
+
+def test_constants_match_header():
+    import re
+    text = open(_native.HEADER).read()
+    defs = dict(re.findall(r"#define\s+(SOLVE_\w+)\s+\(?(-?\w+)u?\)?", text))
+    assert int(defs["SOLVE_OK"]) == api.OK
+    assert int(defs["SOLVE_E_ARG"]) == api.E_ARG
+    assert int(defs["SOLVE_E_SIZE"]) == api.E_SIZE
+    assert int(defs["SOLVE_E_ORDER"]) == api.E_ORDER
+    assert int(defs["SOLVE_E_BUDGET"]) == api.E_BUDGET
+    assert int(defs["SOLVE_E_DEVICE"]) == api.E_DEVICE
+    assert int(defs["SOLVE_E_TICKET"]) == api.E_TICKET
+    assert int(defs["SOLVE_E_STATE"]) == api.E_STATE
+    assert int(defs["SOLVE_MAX_N_BLOCK"]) == api.MAX_N_BLOCK
+    assert int(defs["SOLVE_MAX_N_BATCH"]) == api.MAX_N_BATCH
+    assert int(defs["SOLVE_PLAIN"].rstrip("u")) == api.PLAIN
+
+
+def test_argument_errors_need_no_device(lib):
+    p = C.c_void_p(0x1000)  # never dereferenced: the calls fail on their arguments first
+    assert lib.spline_build(None, p, 10, 0.0, 0.0, p, None, None) == api.E_ARG
+    assert lib.spline_build(p, p, 2, 0.0, 0.0, p, None, None) == api.E_SIZE
+    assert lib.spline_build(p, p, api.MAX_N_BLOCK + 1, 0.0, 0.0, p, None, None) == api.E_SIZE
+    assert lib.spline_eval_uniform(p, p, p, 10, 0, p, None) == api.E_SIZE
+    assert lib.spline_eval_uniform(p, None, p, 10, 5, p, None) == api.E_ARG
+    assert lib.spline_bracket_uniform(p, 2, 5, p, None) == api.E_SIZE
+    assert lib.spline_noop_uniform(None, 5, 5, p, None) == api.E_ARG
+    assert lib.spline_eval_points(p, p, p, 10, None, 5, p, None, None, None, None) == api.E_ARG
+    assert lib.solve_create(None, None) == api.E_ARG
+    assert lib.solve_poll(None, 1, None) == api.E_ARG
+    assert lib.solve_destroy(None) == api.E_ARG
+    assert lib.spline_plan_destroy(None) == api.E_ARG
+    assert lib.spline_plan_replay(None, None) == api.E_ARG
+    koff = np.array([0, 3], dtype=np.int64)
+    out = C.c_void_p()
+    assert lib.spline_plan_create(0, 1, None, koff.ctypes.data_as(C.c_void_p), 0, None, C.byref(out)) == api.E_ARG
+
+
+def test_create_rejects_bad_config(lib):
+    cfg = _native.SolveConfig(0, 0, 16, 0, 0, 2, None)     # zero budget
+    h = C.c_void_p()
+    assert lib.solve_create(C.byref(cfg), C.byref(h)) == api.E_ARG
+    cfg = _native.SolveConfig(0, 1 << 30, 16, 7, 0, 2, None)  # unknown precision
+    assert lib.solve_create(C.byref(cfg), C.byref(h)) == api.E_ARG
+    cfg = _native.SolveConfig(0, 1 << 30, 16, 0, 1 << 7, 2, None)  # unknown flag
+    assert lib.solve_create(C.byref(cfg), C.byref(h)) == api.E_ARG
+
+
+def test_clock_is_monotonic(lib):
+    a = lib.solve_clock()
+    b = lib.solve_clock()
+    assert b >= a > 0

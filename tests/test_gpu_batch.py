@@ -1,0 +1,187 @@
+"""Parity of the batched form (one persistent fused launch over many curves,
+its two-launch variant, hipGraph capture/replay, the autotuner) with the FP64
+oracle, through the C ABI."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close, dev, host
+from paper_2001_09253_amd import api, workloads as w
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(256, 512), (256, 1024), (256, 2048), (512, 1024), (512, 2048)]
+
+
+def to_dev(b, status=True):
+    bufs = {"x": dev(b.x), "y": dev(b.y), "sd": dev(b.sd), "ed": dev(b.ed),
+            "koff": dev(b.koff, torch.int64), "qoff": dev(b.qoff, torch.int64),
+            "yq": torch.full((int(b.qoff[-1]),), np.nan, dtype=torch.float64, device="cuda"),
+            "ypp": torch.full((int(b.koff[-1]),), np.nan, dtype=torch.float64, device="cuda")}
+    st = torch.full((b.count,), 99, dtype=torch.int32, device="cuda") if status else None
+    return bufs, st
+
+
+def check_batch(b, yq, ypp, o=None, what=""):
+    if o is None:
+        o = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
+    o_yq, o_ypp, o_st, _ = o
+    assert np.all(o_st == 0)
+    for i in range(b.count):
+        k0, k1 = b.koff[i], b.koff[i + 1]
+        q0, q1 = b.qoff[i], b.qoff[i + 1]
+        assert_close(ypp[k0:k1], o_ypp[k0:k1], "%s ypp inst %d" % (what, i))
+        assert_close(yq[q0:q1], o_yq[q0:q1], "%s yq inst %d" % (what, i))
+    return o
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    return w.batch(seed=3, count=300)
+
+
+@pytest.fixture(scope="module")
+def small_batch_oracle(small_batch):
+    b = small_batch
+    return oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_batch_matches_oracle(small_batch, small_batch_oracle, shape, fused):
+    b = small_batch
+    t = api.Tuning(shape[0], shape[1], 2, fused)
+    plan = api.spline_plan_create(b.koff, b.qoff, tuning=t)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    assert np.all(host(st) == 0)
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), small_batch_oracle, "shape %s fused %d" % (shape, fused))
+
+
+def test_batch_mixed_sizes_up_to_limit():
+    # curves of every build kind: one per wavefront (n <= 512) and whole
+    # workgroup (up to the batch limit), ragged query counts
+    n = np.array([3, 4, 5, 13, 64, 65, 511, 512, 513, 1000, 2047, api.MAX_N_BATCH, 3, 130], dtype=np.int64)
+    m = np.array([1, 2, 3, 2048, 1023, 1025, 7, 4096, 1, 50000, 333, 2049, 100000, 17], dtype=np.int64)
+    b = w.batch_from_sizes(17, n, m)
+    for shape in ((256, 1024), (512, 2048)):
+        plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(shape[0], shape[1], 1, 1))
+        bufs, st = to_dev(b)
+        api.spline_plan_run(plan, bufs, st)
+        check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="mixed %s" % (shape,))
+
+
+def test_batch_single_instance_equals_plain_sizes():
+    b = w.batch_from_sizes(5, np.array([13]), np.array([2048]))
+    plan = api.spline_plan_create(b.koff, b.qoff)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="single")
+
+
+def test_batch_invalid_instance_flags_status():
+    b = w.batch(seed=4, count=40)
+    x = b.x.copy()
+    bad = 7
+    x[b.koff[bad] + 1] = x[b.koff[bad]]          # repeated knot in curve 7
+    b2 = w.Batch(b.koff, b.qoff, x, b.y, b.sd, b.ed)
+    plan = api.spline_plan_create(b2.koff, b2.qoff)
+    bufs, st = to_dev(b2)
+    api.spline_plan_run(plan, bufs, st)
+    s = host(st)
+    assert s[bad] == api.E_ORDER
+    assert np.all(np.delete(s, bad) == 0)
+    ypp = host(bufs["ypp"])
+    assert np.all(np.isnan(ypp[b.koff[bad]:b.koff[bad + 1]]))
+
+
+def test_plan_rejects_bad_sizes():
+    with pytest.raises(api.SolveError) as e:
+        api.spline_plan_create([0, 2], [0, 10])
+    assert e.value.code == api.E_SIZE
+    with pytest.raises(api.SolveError) as e:
+        api.spline_plan_create([0, api.MAX_N_BATCH + 1], [0, 10])
+    assert e.value.code == api.E_SIZE
+    with pytest.raises(api.SolveError) as e:
+        api.spline_plan_create([0, 5], [0, 0])
+    assert e.value.code == api.E_SIZE
+    with pytest.raises(api.SolveError) as e:
+        api.spline_plan_create([0, 5], [0, 10], tuning=api.Tuning(128, 1024, 2, 1))
+    assert e.value.code == api.E_ARG
+
+
+def test_graph_replays_match_eager(small_batch, small_batch_oracle):
+    b = small_batch
+    plan = api.spline_plan_create(b.koff, b.qoff)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    eager_yq, eager_ypp = host(bufs["yq"]).copy(), host(bufs["ypp"]).copy()
+    stream = torch.cuda.Stream()
+    api.spline_plan_capture(plan, bufs, st, stream=stream)
+    for r in range(4):
+        bufs["yq"].fill_(np.nan)
+        bufs["ypp"].fill_(np.nan)
+        torch.cuda.synchronize()
+        api.spline_plan_replay(plan, stream=stream)
+        stream.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(bufs["yq"]), eager_yq)
+        np.testing.assert_array_equal(host(bufs["ypp"]), eager_ypp)
+        assert np.all(host(st) == 0)
+    del junk
+    check_batch(b, eager_yq, eager_ypp, small_batch_oracle, "graph")
+
+
+def test_autotune_picks_a_valid_tuning_and_caches(small_batch, small_batch_oracle):
+    b = small_batch
+    plan = api.spline_plan_create(b.koff, b.qoff)
+    bufs, st = to_dev(b)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        best, ms = api.spline_plan_autotune(plan, bufs, reps=3, cache_path=path)
+        assert ms > 0
+        assert (best.block, best.queries_per_tile) in SHAPES
+        assert os.path.exists(path)
+        got = api.spline_plan_get_tuning(plan)
+        assert (got.block, got.queries_per_tile, got.grid_per_cu, got.fused) == \
+            (best.block, best.queries_per_tile, best.grid_per_cu, best.fused)
+        # a second tune hits the cache
+        best2, ms2 = api.spline_plan_autotune(plan, bufs, reps=3, cache_path=path)
+        assert (best2.block, best2.queries_per_tile, best2.grid_per_cu, best2.fused) == \
+            (best.block, best.queries_per_tile, best.grid_per_cu, best.fused)
+        assert ms2 == pytest.approx(ms, rel=1e-5)
+    api.spline_plan_run(plan, bufs, st)
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), small_batch_oracle, "tuned")
+
+
+def test_full_batched_config():
+    b = w.batch(seed=0)
+    plan = api.spline_plan_create(b.koff, b.qoff)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    assert np.all(host(st) == 0)
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="4096 curves")
+
+
+def test_batch_result_independent_of_company():
+    # the same curve alone and inside a batch gives identical bits
+    b = w.batch(seed=6, count=64)
+    plan = api.spline_plan_create(b.koff, b.qoff)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    all_yq, all_ypp = host(bufs["yq"]), host(bufs["ypp"])
+    for i in (0, 5, 63):
+        inst = b.instance(i)
+        bi = w.Batch(np.array([0, inst.n]), np.array([0, inst.m]), inst.x, inst.y, np.array([inst.start_deriv]),
+                     np.array([inst.end_deriv]))
+        p1 = api.spline_plan_create(bi.koff, bi.qoff)
+        b1, s1 = to_dev(bi)
+        api.spline_plan_run(p1, b1, s1)
+        np.testing.assert_array_equal(host(b1["yq"]), all_yq[b.qoff[i]:b.qoff[i + 1]])
+        np.testing.assert_array_equal(host(b1["ypp"]), all_ypp[b.koff[i]:b.koff[i + 1]])
