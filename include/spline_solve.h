@@ -73,6 +73,7 @@ extern "C" {
 /* ---- limits ------------------------------------------------------------------- */
 #define SOLVE_MAX_N_BLOCK 16384   /* largest n one workgroup solves (plain path) */
 #define SOLVE_MAX_N_BATCH 2048    /* largest n of an instance in a fused batch   */
+#define SOLVE_MAX_N_SOLVE 1073741824  /* largest n of spline_solve_uniform (2^30) */
 
 typedef struct solve_ctx solve_ctx;
 typedef uint64_t solve_ticket;
@@ -169,6 +170,22 @@ int spline_build(const double *x, const double *y, int64_t n, double start_deriv
  * Errors: E_ARG, E_SIZE (n < 3 or m < 1). */
 int spline_eval_uniform(const double *x, const double *y, const double *ypp, int64_t n,
                         int64_t m, double *yq, void *stream);
+
+/* Steps a1-a6 for one curve in a single launch, with no synchronisation
+ * between workgroups: each workgroup owns a block of knot intervals, solves
+ * the paper's rows over that block plus 128 rows on either side (coupling
+ * beyond them dropped; by the diagonal dominance the paper proves, this
+ * changes y'' by less than 1e-21 max|y''|, and curves of up to 2*128 + 1
+ * rows more than a block are solved whole), then evaluates the uniform
+ * queries that fall in its intervals.
+ * x, y: n device doubles; yq: m device doubles (output); ypp: nullable, n
+ * device doubles (output).  status: nullable device int32 that the call
+ * leaves unchanged unless it finds unordered knots, in which case it is set
+ * to SOLVE_E_ORDER and the outputs are unspecified (initialise it to
+ * SOLVE_OK).  Errors: E_ARG, E_SIZE (n < 3, n > SOLVE_MAX_N_SOLVE, m < 1). */
+int spline_solve_uniform(const double *x, const double *y, int64_t n, double start_deriv,
+                         double end_deriv, int64_t m, double *yq, double *ypp, int32_t *status,
+                         void *stream);
 
 /* Step a5 alone: the interval index of each of the m uniform queries
  * (int32, device, output), computed by the same code as spline_eval_uniform. */

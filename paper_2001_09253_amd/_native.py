@@ -46,6 +46,7 @@ SIGNATURES = {
     "solve_inject_fault": (C.c_int, [_vp]),
     "solve_destroy": (C.c_int, [_vp]),
     "spline_build": (C.c_int, [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp]),
+    "spline_solve_uniform": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _vp, _vp, _vp, _vp]),
     "spline_eval_uniform": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
     "spline_bracket_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),
     "spline_noop_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),
@@ -66,7 +67,7 @@ def header_functions():
     with open(HEADER) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:int|double)\s+\**\s*(\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(?:int|double|uint64_t)\s+\**\s*(\w+)\s*\(", text)))
 
 
 def lib():

@@ -23,6 +23,7 @@ FP64, FP32_REFINE = 0, 1
 PLAIN, NO_GRAPH = 1, 2
 MAX_N_BLOCK = 16384
 MAX_N_BATCH = 2048
+MAX_N_SOLVE = 1 << 30
 
 _NAMES = {OK: "OK", E_ARG: "E_ARG", E_SIZE: "E_SIZE", E_ORDER: "E_ORDER", E_BUDGET: "E_BUDGET",
           E_DEVICE: "E_DEVICE", E_TICKET: "E_TICKET", E_STATE: "E_STATE"}
@@ -86,6 +87,18 @@ def spline_build(x, y, start_deriv, end_deriv, ypp, status=None, stream=None):
                                       float(end_deriv), _dev(ypp, name="ypp", numel=n),
                                       _dev(status, torch.int32, "status", 1, optional=True), _stream(stream)),
            "spline_build")
+
+
+def spline_solve_uniform(x, y, start_deriv, end_deriv, m, yq, ypp=None, status=None, stream=None):
+    """Build and evaluate one curve in a single launch (status, if given, is
+    set to E_ORDER on unordered knots and left as is otherwise)."""
+    n = x.numel()
+    _check(_native.lib().spline_solve_uniform(_dev(x, name="x"), _dev(y, name="y", numel=n), n, float(start_deriv),
+                                              float(end_deriv), int(m), _dev(yq, name="yq", numel=int(m)),
+                                              _dev(ypp, name="ypp", numel=n, optional=True),
+                                              _dev(status, torch.int32, "status", 1, optional=True),
+                                              _stream(stream)),
+           "spline_solve_uniform")
 
 
 def spline_eval_uniform(x, y, ypp, m, yq, stream=None):

@@ -18,6 +18,7 @@
 namespace spl {
 
 constexpr int kSpinLimit = 1 << 25;  // ~ seconds of s_sleep before a tile gives up waiting
+constexpr int kBatchWin = 256;       // staged knot window of an evaluate tile
 
 template <int BLOCK, int QPT>
 struct FusedSmem {
@@ -26,7 +27,7 @@ struct FusedSmem {
     static constexpr int kBuildDoubles =
         (BLOCK * kCHB > kNW * kWaveBuildMaxN) ? BLOCK * kCHB : kNW * kWaveBuildMaxN;
     union {
-        EvalSmem<BLOCK, QPT> ev;
+        UniSmem<BLOCK, QPT, kBatchWin> ev;
         double build[kBuildDoubles];
     };
     Fwd lds_f[kNW];
@@ -48,11 +49,6 @@ __device__ void run_build_item(const BatchDevArgs& a, const BuildItem& bi, Fused
         const int n = (int)(a.koff[i + 1] - o);
         build_group<BLOCK, S::kCHB, false>(a.x + o, a.y + o, n, a.sd[i], a.ed[i], a.ypp + o,
                                            a.status ? a.status + i : nullptr, sm.build, sm.lds_f, sm.lds_b, tid);
-        if (signal) {
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) __hip_atomic_store(&a.ready[i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
     } else {
         const int i = wid < kItemLanes ? bi.inst[wid] : -1;
         if (i >= 0) {
@@ -62,11 +58,16 @@ __device__ void run_build_item(const BatchDevArgs& a, const BuildItem& bi, Fused
                                                              a.status ? a.status + i : nullptr,
                                                              sm.build + wid * kWaveBuildMaxN, nullptr, nullptr,
                                                              lane);
-            if (signal) {
-                __threadfence();
-                wave_sync();
-                if (lane == 0) __hip_atomic_store(&a.ready[i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        }
+    }
+    if (signal) {
+        // one release for the whole item, then its curves' ready flags
+        __syncthreads();
+        if (tid == 0) release_fence_agent();
+        __syncthreads();
+        if (tid < kItemLanes) {
+            const int i = bi.kind == kItemWhole ? (tid == 0 ? bi.inst[0] : -1) : bi.inst[tid];
+            if (i >= 0) __hip_atomic_store(&a.ready[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -78,7 +79,7 @@ __device__ void run_tile(const BatchDevArgs& a, const TileItem& ti, FusedSmem<BL
     const int64_t n = a.koff[i + 1] - o;
     const int64_t qo = a.qoff[i];
     const int64_t m = a.qoff[i + 1] - qo;
-    eval_uniform_tile<BLOCK, QPT, kModeValue, false>(a.x + o, a.y + o, a.ypp + o, n, m,
+    eval_uniform_tile<BLOCK, QPT, kBatchWin, kModeValue, false>(a.x + o, a.y + o, a.ypp + o, n, m,
                                                      (int64_t)ti.local * (BLOCK * QPT), a.yq + qo, sm.ev,
                                                      threadIdx.x);
 }
@@ -100,16 +101,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     // Phase 2: evaluate tiles with a grid stride, each after its curve is ready.
     for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const TileItem ti = a.tiles[t];
-        if (tid == 0) {
-            int spins = 0;
-            while (__hip_atomic_load(&a.ready[ti.inst], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
-                    __hip_atomic_store(&a.counters[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
+        if (tid == 0) (void)wait_flag_at_least<2>(&a.ready[ti.inst], 1, kSpinLimit, &a.counters[1]);
         __syncthreads();
         run_tile<BLOCK, QPT>(a, ti, sm);
         __syncthreads();

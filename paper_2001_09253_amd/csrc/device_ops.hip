@@ -18,14 +18,14 @@ __global__ __launch_bounds__(NT) void build_kernel(const double* __restrict__ x,
     build_group<NT, CH, false>(x, y, n, sd, ed, ypp, status, lds, lds_f, lds_b, threadIdx.x);
 }
 
-template <int BLOCK, int QPT, int MODE, bool NT_STORE>
+template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE>
 __global__ __launch_bounds__(BLOCK) void eval_uniform_kernel(const double* __restrict__ x,
                                                              const double* __restrict__ y,
                                                              const double* __restrict__ ypp, int64_t n,
                                                              int64_t m, void* __restrict__ out) {
-    __shared__ EvalSmem<BLOCK, QPT> sm;
+    __shared__ UniSmem<BLOCK, QPT, WIN> sm;
     const int64_t k0 = (int64_t)blockIdx.x * (BLOCK * QPT);
-    eval_uniform_tile<BLOCK, QPT, MODE, NT_STORE>(x, y, ypp, n, m, k0, out, sm, threadIdx.x);
+    eval_uniform_tile<BLOCK, QPT, WIN, MODE, NT_STORE>(x, y, ypp, n, m, k0, out, sm, threadIdx.x);
 }
 
 template <int BLOCK, int QPT>
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
                                                             const double* __restrict__ xq, int64_t m,
                                                             double* __restrict__ yq, double* __restrict__ d1,
                                                             double* __restrict__ d2, int32_t* __restrict__ idx) {
-    __shared__ EvalSmem<BLOCK, QPT> sm;
+    __shared__ EvalSmem<BLOCK, QPT, BLOCK * QPT + 2> sm;
     __shared__ double red[3 * (BLOCK / kWave)];
     const int64_t k0 = (int64_t)blockIdx.x * (BLOCK * QPT);
     eval_points_tile<BLOCK, QPT>(x, y, ypp, n, xq, m, k0, yq, d1, d2, idx, sm, red, threadIdx.x);
@@ -50,21 +50,37 @@ int launch_build(const double* x, const double* y, int64_t n, double sd, double 
     else if (n <= 1024) build_kernel<256, 4><<<1, 256, 0, s>>>(x, y, ni, sd, ed, ypp, status);
     else if (n <= 4096) build_kernel<1024, 4><<<1, 1024, 0, s>>>(x, y, ni, sd, ed, ypp, status);
     else if (n <= 8192) build_kernel<1024, 8><<<1, 1024, 0, s>>>(x, y, ni, sd, ed, ypp, status);
+    else if (n <= 13312) build_kernel<1024, 13><<<1, 1024, 0, s>>>(x, y, ni, sd, ed, ypp, status);
     else build_kernel<1024, 16><<<1, 1024, 0, s>>>(x, y, ni, sd, ed, ypp, status);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
 constexpr int kEvalBlock = 256;
-constexpr int kEvalQpt = 4;
+constexpr int kEvalQpt = 4;   // explicit queries
+constexpr int kEvalWin = 256; // staged window of the uniform tiles
 
+template <int QPT, int WIN, int MODE>
+int launch_eval_uniform_q(const double* x, const double* y, const double* ypp, int64_t n, int64_t m, void* out,
+                          hipStream_t s) {
+    constexpr int Q = kEvalBlock * QPT;
+    const int64_t tiles = (m + Q - 1) / Q;
+    if (tiles > 0x7fffffffLL) return SOLVE_E_SIZE;
+    eval_uniform_kernel<kEvalBlock, QPT, WIN, MODE, false><<<(unsigned)tiles, kEvalBlock, 0, s>>>(x, y, ypp, n, m,
+                                                                                                  out);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
+// Tile size from the query density: a tile should span at most half of the
+// staged window's knots, so that the guessed window usually covers it.
 template <int MODE>
 int launch_eval_uniform(const double* x, const double* y, const double* ypp, int64_t n, int64_t m, void* out,
                         hipStream_t s) {
-    constexpr int Q = kEvalBlock * kEvalQpt;
-    const int64_t tiles = (m + Q - 1) / Q;
-    if (tiles > 0x7fffffffLL) return SOLVE_E_SIZE;
-    eval_uniform_kernel<kEvalBlock, kEvalQpt, MODE, false><<<(unsigned)tiles, kEvalBlock, 0, s>>>(x, y, ypp, n, m, out);
-    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+    const double knots_per_query = (double)(n - 1) / (double)(m > 1 ? m - 1 : 1);
+    const double half = 0.5 * kEvalWin;
+    if (knots_per_query * (kEvalBlock * 8) <= half) return launch_eval_uniform_q<8, kEvalWin, MODE>(x, y, ypp, n, m, out, s);
+    if (knots_per_query * (kEvalBlock * 4) <= half) return launch_eval_uniform_q<4, kEvalWin, MODE>(x, y, ypp, n, m, out, s);
+    if (knots_per_query * (kEvalBlock * 2) <= half) return launch_eval_uniform_q<2, kEvalWin, MODE>(x, y, ypp, n, m, out, s);
+    return launch_eval_uniform_q<1, 2 * kEvalWin, MODE>(x, y, ypp, n, m, out, s);
 }
 
 int launch_eval_uniform_values(const double* x, const double* y, const double* ypp, int64_t n, int64_t m,

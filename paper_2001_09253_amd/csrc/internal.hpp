@@ -13,4 +13,7 @@ int launch_eval_uniform_values(const double* x, const double* y, const double* y
 int launch_eval_points(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
                        int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s);
 
+int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
+                         double* ypp, int32_t* status, hipStream_t s);
+
 }  // namespace spl

@@ -186,6 +186,31 @@ __device__ __forceinline__ Fwd fwd_apply_row(const Fwd& A, double a, double b, d
     return fwd_normalize(o);
 }
 
+// One Thomas row applied after A, without renormalising (the caller scales
+// the row so that the entries stay within a factor 1.5 per row).
+__device__ __forceinline__ Fwd fwd_apply_row_raw(const Fwd& A, double a, double b, double c, double d) {
+    Fwd o;
+    o.m00 = c * A.m10;
+    o.m01 = c * A.m11;
+    o.m10 = b * A.m10 - a * A.m00;
+    o.m11 = b * A.m11 - a * A.m01;
+    o.r0 = d * A.m10 - a * A.r0;
+    o.r1 = d * A.m11 - a * A.r1;
+    o.al = -a * A.al;
+    return o;
+}
+
+// 1/d from the hardware reciprocal estimate refined by two Newton steps
+// (error below one unit in the last place, no IEEE division sequence).
+__device__ __forceinline__ double fast_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return r;
+}
+
 // Outer applied to the result of inner: y -> O.K (I.K y + I.H) + O.H.
 __device__ __forceinline__ Bwd bwd_compose(const Bwd& O, const Bwd& I) {
     return Bwd{O.K * I.K, O.K * I.H + O.H};
@@ -197,6 +222,64 @@ __device__ __forceinline__ Fwd shfl_up_fwd(const Fwd& v, int d) {
 }
 __device__ __forceinline__ Bwd shfl_down_bwd(const Bwd& v, int d) {
     return Bwd{__shfl_down(v.K, d), __shfl_down(v.H, d)};
+}
+
+// Compose without renormalising (the caller bounds the growth).
+__device__ __forceinline__ Fwd fwd_compose_raw(const Fwd& B, const Fwd& A) {
+    Fwd o;
+    o.m00 = B.m00 * A.m00 + B.m01 * A.m10;
+    o.m01 = B.m00 * A.m01 + B.m01 * A.m11;
+    o.m10 = B.m10 * A.m00 + B.m11 * A.m10;
+    o.m11 = B.m10 * A.m01 + B.m11 * A.m11;
+    o.r0 = B.r0 * A.m00 + B.r1 * A.m10 + B.al * A.r0;
+    o.r1 = B.r0 * A.m01 + B.r1 * A.m11 + B.al * A.r1;
+    o.al = B.al * A.al;
+    return o;
+}
+
+template <bool NORM>
+__device__ __forceinline__ Fwd fwd_comp(const Fwd& B, const Fwd& A) {
+    if constexpr (NORM) return fwd_compose(B, A); else return fwd_compose_raw(B, A);
+}
+
+// Data-parallel-primitive lane moves (DPP) of a double: lanes whose source
+// lane is outside the pattern, or whose row is masked off, receive `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const long long vi = __double_as_longlong(v);
+    const long long oi = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ Fwd dpp_fwd(const Fwd& v) {
+    return Fwd{dpp_f64<CTRL, ROW_MASK>(1.0, v.m00), dpp_f64<CTRL, ROW_MASK>(0.0, v.m01),
+               dpp_f64<CTRL, ROW_MASK>(0.0, v.m10), dpp_f64<CTRL, ROW_MASK>(1.0, v.m11),
+               dpp_f64<CTRL, ROW_MASK>(0.0, v.r0),  dpp_f64<CTRL, ROW_MASK>(0.0, v.r1),
+               dpp_f64<CTRL, ROW_MASK>(1.0, v.al)};
+}
+
+// DPP controls (GFX9): shift right within rows of 16 lanes, broadcast lane 15
+// of a row to the next row, lane 31 to rows 2 and 3, shift the wave by one.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+// Inclusive and exclusive prefix (in lane order, later lanes outer) of Fwd
+// maps over one wavefront with DPP moves (no LDS round trips): a Hillis-Steele
+// scan inside each row of 16 lanes, then the row broadcasts.  Lanes that
+// receive nothing get the identity, so every lane runs the same compose.
+template <bool NORM>
+__device__ __forceinline__ Fwd wave_excl_prefix_fwd_dpp(Fwd v, Fwd* incl_out) {
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr1, 0xf>(v));
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr2, 0xf>(v));
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr4, 0xf>(v));
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr8, 0xf>(v));
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowBcast15, 0xa>(v));
+    v = fwd_comp<NORM>(v, dpp_fwd<kDppRowBcast31, 0xc>(v));
+    *incl_out = v;
+    return dpp_fwd<kDppWaveShr1, 0xf>(v);
 }
 
 // Exclusive prefix (in lane order) of Fwd maps over one wavefront.
@@ -222,6 +305,29 @@ __device__ __forceinline__ Bwd wave_excl_suffix_bwd(Bwd v, int lane, Bwd* incl_o
     Bwd ex = shfl_down_bwd(v, 1);
     return lane == kWave - 1 ? bwd_identity() : ex;
 }
+
+// Cross-workgroup signalling.  On a multi-XCD device an agent-scope acquire
+// or release maintains the XCD's L2 (write back / invalidate), so a poll loop
+// must not acquire on every iteration: it polls with relaxed atomic loads and
+// acquires once, and a producer publishes with one release fence per
+// workgroup (after a barrier that orders the other lanes' stores).
+template <int SLEEP>
+__device__ __forceinline__ bool wait_flag_at_least(int32_t* flag, int32_t target, int limit, int32_t* timeout) {
+    int spins = 0;
+    bool ok = true;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(SLEEP);
+        if (++spins > limit) {
+            if (timeout) __hip_atomic_store(timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+__device__ __forceinline__ void release_fence_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -257,43 +363,78 @@ __device__ __forceinline__ void row_coeffs(int j, int n, bool nat_s, bool nat_e,
 }
 
 // ---------------------------------------------------------------------------
-// The build of one instance by a group of NT lanes (a whole workgroup, or one
-// wavefront when WAVE_ONLY), each lane owning at most CH consecutive rows.
-//   lds:   >= n doubles of group-private LDS (staging of x, then y, then y'')
-//   lds_f, lds_b: NT/64 scan slots (unused when WAVE_ONLY)
-// Requires 3 <= n <= NT*CH.  Writes ypp[0..n) and, if status, *status.
+// Cross-group policies of the build.  A curve's rows are split over one or
+// more groups (a wavefront, a workgroup, or several workgroups); inside a
+// group lanes own chunks and scan in-group, and the policy supplies what the
+// other groups contribute: the forward map of all rows before the group, the
+// backward map of all rows after it, and whether any group saw bad knots.
 // ---------------------------------------------------------------------------
-template <int NT, int CH, bool WAVE_ONLY>
-__device__ void build_group(const double* __restrict__ x, const double* __restrict__ y, int n, double sd,
-                            double ed, double* __restrict__ ypp, int32_t* __restrict__ status, double* lds,
-                            Fwd* lds_f, Bwd* lds_b, int tid) {
+struct SoloGroup {  // the group holds every row of the curve
+    __device__ void publish_forward(const Fwd&) const {}
+    __device__ Fwd forward_before(int) const { return fwd_identity(); }
+    __device__ void publish_backward(const Bwd&) const {}
+    __device__ Bwd backward_after(int) const { return bwd_identity(); }
+    __device__ void publish_bad(bool) const {}
+    __device__ bool any_bad(bool local) const { return local; }
+};
+
+// ---------------------------------------------------------------------------
+// The build of rows [rs, re) of one curve by a group of NT lanes (a whole
+// workgroup, or one wavefront when WAVE_ONLY), each lane owning at most CH
+// consecutive rows.
+//   lds:   >= re - rs + 2 doubles of group-private LDS (staging of x, then y,
+//          then y'')
+//   lds_f, lds_b: NT/64 scan slots (unused when WAVE_ONLY)
+//   cross: the policy above (SoloGroup when rs = 0 and re = n)
+//   lds_y, lds_out: optional separate LDS buffers (>= re - rs + 2 doubles)
+//          for y and for the result; with lds_y, x and y are staged in one
+//          load round and both stay staged (knot j at [j - max(rs-1, 0)]);
+//          with lds_out the result is left there as lds_out[i - rs]
+// Requires 3 <= n and re - rs <= NT*CH.  Writes ypp[rs..re) when ypp is not
+// null; the group that owns row 0 writes *status (if status).  Returns
+// whether the knots were found unordered.
+// ---------------------------------------------------------------------------
+template <int NT, int CH, bool WAVE_ONLY, typename Cross, bool NORM = true>
+__device__ bool build_span(const double* __restrict__ x, const double* __restrict__ y, int n, int rs, int re,
+                           double sd, double ed, double* __restrict__ ypp, int32_t* __restrict__ status,
+                           double* lds, Fwd* lds_f, Bwd* lds_b, const Cross& cross, int tid,
+                           double* lds_y = nullptr, double* lds_out = nullptr) {
     static_assert(NT % kWave == 0, "group must be whole wavefronts");
     constexpr int NW = NT / kWave;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
     const bool nat_s = natural_end(sd);
     const bool nat_e = natural_end(ed);
-    const int r = (n + NT - 1) / NT;
-    const int s = tid * r;
-    const int cnt = max(0, min(n, s + r) - s);
+    const int nb = max(0, re - rs);
+    const int r = (nb + NT - 1) / NT;
+    const int s = rs + tid * r;
+    const int cnt = max(0, min(re, s + r) - s);
+    const int lo = max(rs - 1, 0);       // first staged knot
+    const int hi = min(re, n - 1);       // last staged knot
+    // knot j lives in lds[j - lo]
 
     // a1: widths and validation (x staged through LDS, coalesced).
-    for (int i = tid; i < n; i += NT) lds[i] = x[i];
+    const bool split = lds_y != nullptr;
+    double* sy = split ? lds_y : lds;
+    for (int i = lo + tid; i <= hi; i += NT) {
+        lds[i - lo] = x[i];
+        if (split) sy[i - lo] = y[i];
+    }
     group_sync<WAVE_ONLY>();
     bool bad = false;
     double w[CH];
     double d[CH];
     double wprev0 = 0.0;
     {
-        double xprev = (cnt > 0 && s >= 1) ? lds[s - 1] : 0.0;
+        double xprev = (cnt > 0 && s >= 1) ? lds[s - 1 - lo] : 0.0;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             if (i < cnt) {
                 const int j = s + i;
-                const double xj = lds[j];
+                const double xj = lds[j - lo];
                 if (j >= 1 && !(xj > xprev)) bad = true;
                 if (i == 0) wprev0 = (j >= 1) ? xj - xprev : 0.0;
-                w[i] = (j + 1 < n) ? lds[j + 1] - xj : 0.0;
+                w[i] = (j + 1 < n) ? lds[j + 1 - lo] - xj : 0.0;
                 xprev = xj;
             } else {
                 w[i] = 0.0;
@@ -301,23 +442,22 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
         }
     }
     bad = group_any<WAVE_ONLY>(bad);
-    if (bad) {
-        for (int i = tid; i < n; i += NT) ypp[i] = __builtin_nan("");
-        if (status && tid == 0) *status = kStatusOrder;
-        return;
-    }
+    cross.publish_bad(bad);
 
-    // a1/a2: slopes and right-hand sides (y staged through the same LDS).
-    group_sync<WAVE_ONLY>();
-    for (int i = tid; i < n; i += NT) lds[i] = y[i];
-    group_sync<WAVE_ONLY>();
+    // a1/a2: slopes and right-hand sides (y staged through the same LDS
+    // unless it has its own buffer).
+    if (!split) {
+        group_sync<WAVE_ONLY>();
+        for (int i = lo + tid; i <= hi; i += NT) sy[i - lo] = y[i];
+        group_sync<WAVE_ONLY>();
+    }
     {
-        double sprev = (cnt > 0 && s >= 1) ? (lds[s] - lds[s - 1]) / wprev0 : 0.0;
+        double sprev = (cnt > 0 && s >= 1) ? (sy[s - lo] - sy[s - 1 - lo]) * fast_rcp(wprev0) : 0.0;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             if (i < cnt) {
                 const int j = s + i;
-                const double snext = (j + 1 < n) ? (lds[j + 1] - lds[j]) / w[i] : 0.0;
+                const double snext = (j + 1 < n) ? (sy[j + 1 - lo] - sy[j - lo]) * fast_rcp(w[i]) : 0.0;
                 double dj;
                 if (j == 0) dj = nat_s ? 0.0 : 6.0 * (snext - sd);
                 else if (j == n - 1) dj = nat_e ? 0.0 : 6.0 * (ed - sprev);
@@ -339,20 +479,40 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
             if (i < cnt) {
                 double a, b, c;
                 row_coeffs(s + i, n, nat_s, nat_e, wa, w[i], &a, &b, &c);
-                acc = fwd_apply_row(acc, a, b, c, d[i]);
+                // scale the row by 2^-e, e the exponent of b (exact; the map
+                // is projective): the entries then grow by at most 1.5 a row
+                int e;
+                (void)frexp(b, &e);
+                acc = fwd_apply_row_raw(acc, ldexp(a, -e), ldexp(b, -e), ldexp(c, -e), ldexp(d[i], -e));
                 wa = w[i];
             }
         }
+        if constexpr (NORM) acc = fwd_normalize(acc);
     }
+    // Without NORM the scans compose up to NT*CH scaled rows unnormalised:
+    // entries stay within 1.5^rows and 0.375^rows of 1, which the caller
+    // keeps inside the double range (a few hundred rows).
     Fwd incl;
-    Fwd pre = wave_excl_prefix_fwd(acc, lane, &incl);
+    Fwd pre = wave_excl_prefix_fwd_dpp<NORM>(acc, &incl);
     if constexpr (!WAVE_ONLY) {
         if (lane == kWave - 1) lds_f[wid] = incl;
         __syncthreads();
-        Fwd pw = fwd_identity();
-        for (int w2 = 0; w2 < wid; ++w2) pw = fwd_compose(lds_f[w2], pw);
-        pre = fwd_compose(pre, pw);
+        // exclusive prefix of the wave totals: lanes below NW hold the totals
+        // of the waves before this one (identity elsewhere), scanned in-wave
+        Fwd t = (lane < wid) ? lds_f[lane] : fwd_identity();
+#pragma unroll
+        for (int dd = 1; dd < NW; dd <<= 1) {
+            Fwd o = shfl_up_fwd(t, dd);
+            if (lane >= dd) t = fwd_comp<NORM>(t, o);
+        }
+        const Fwd pw = Fwd{__shfl(t.m00, NW - 1), __shfl(t.m01, NW - 1), __shfl(t.m10, NW - 1),
+                           __shfl(t.m11, NW - 1), __shfl(t.r0, NW - 1), __shfl(t.r1, NW - 1),
+                           __shfl(t.al, NW - 1)};
+        pre = fwd_comp<NORM>(pre, pw);
     }
+    // the group's own total is the last lane's inclusive prefix
+    if (tid == NT - 1) cross.publish_forward(fwd_compose(acc, pre));
+    pre = fwd_comp<NORM>(pre, cross.forward_before(tid));
     // State entering the chunk is pre applied to (P, Q, D) = (0, 1, 0).
     double cp = pre.m01 / pre.m11;
     double dp = pre.r1 / pre.m11;
@@ -366,7 +526,7 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
                 double a, b, c;
                 const double wc = w[i];
                 row_coeffs(s + i, n, nat_s, nat_e, wa, wc, &a, &b, &c);
-                const double inv = 1.0 / (b - a * cp);
+                const double inv = fast_rcp(b - a * cp);
                 cp = c * inv;
                 dp = (d[i] - a * dp) * inv;
                 w[i] = cp;
@@ -387,10 +547,18 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
     if constexpr (!WAVE_ONLY) {
         if (lane == 0) lds_b[wid] = bincl;
         __syncthreads();
-        Bwd pw = bwd_identity();
-        for (int w2 = NW - 1; w2 > wid; --w2) pw = bwd_compose(lds_b[w2], pw);
+        // suffix of the totals of the waves after this one, scanned in-wave
+        Bwd t = (lane < NW && lane > wid) ? lds_b[lane] : bwd_identity();
+#pragma unroll
+        for (int dd = 1; dd < NW; dd <<= 1) {
+            Bwd o = shfl_down_bwd(t, dd);
+            if (lane + dd < kWave) t = bwd_compose(t, o);
+        }
+        const Bwd pw = Bwd{__shfl(t.K, 0), __shfl(t.H, 0)};
         suf = bwd_compose(suf, pw);
     }
+    if (tid == 0) cross.publish_backward(bwd_compose(bacc, suf));
+    suf = bwd_compose(suf, cross.backward_after(tid));
     // y'' just after the chunk (its value does not matter for the last chunk,
     // whose last row has c' = 0).
     double yv = suf.H;
@@ -401,32 +569,44 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
             d[i] = yv;
         }
     }
-    // Every lane has finished reading the y staging; reuse it for y'' and
-    // store the result coalesced.
-    group_sync<WAVE_ONLY>();
+    const bool any_bad = cross.any_bad(bad);
+    // Every lane has finished reading the staging; stage y'' (in its own
+    // buffer if given) and store it coalesced.
+    double* so = lds_out ? lds_out : lds;
+    const double nan = __builtin_nan("");
+    if (!lds_out) group_sync<WAVE_ONLY>();
 #pragma unroll
     for (int i = 0; i < CH; ++i)
-        if (i < cnt) lds[s + i] = d[i];
+        if (i < cnt) so[s + i - rs] = any_bad ? nan : d[i];
     group_sync<WAVE_ONLY>();
-    for (int i = tid; i < n; i += NT) ypp[i] = lds[i];
-    if (status && tid == 0) *status = kStatusOk;
+    if (ypp)
+        for (int i = rs + tid; i < re; i += NT) ypp[i] = so[i - rs];
+    if (status && rs == 0 && tid == 0) *status = any_bad ? kStatusOrder : kStatusOk;
     (void)NW;
+    return any_bad;
 }
 
+// The whole curve in one group.
+template <int NT, int CH, bool WAVE_ONLY>
+__device__ void build_group(const double* __restrict__ x, const double* __restrict__ y, int n, double sd,
+                            double ed, double* __restrict__ ypp, int32_t* __restrict__ status, double* lds,
+                            Fwd* lds_f, Bwd* lds_b, int tid) {
+    build_span<NT, CH, WAVE_ONLY>(x, y, n, 0, n, sd, ed, ypp, status, lds, lds_f, lds_b, SoloGroup{}, tid);
+}
 
 // ---------------------------------------------------------------------------
 // Evaluate: one tile of QPT*BLOCK consecutive uniform queries per call.
 // ---------------------------------------------------------------------------
 enum EvalMode : int { kModeValue = 0, kModeIndex = 1, kModeNoop = 2 };
 
-template <int BLOCK, int QPT>
+template <int BLOCK, int QPT, int WIN>
 struct EvalSmem {
     static constexpr int kQ = BLOCK * QPT;
-    static constexpr int kWin = kQ + 2;  // knots of a window the LDS can hold
-    double sx[kWin];
-    double sy[kWin];
-    double sp[kWin];
-    double sinv[kWin];
+    static constexpr int kWin = WIN;  // knots of a window the LDS holds
+    double sx[WIN];
+    double sy[WIN];
+    double sp[WIN];
+    double sinv[WIN];
     int64_t win[2];
 };
 
@@ -442,74 +622,192 @@ __device__ __forceinline__ void tile_window(const double* __restrict__ x, int64_
     }
 }
 
-template <int BLOCK, int QPT, int MODE, bool NT_STORE>
-__device__ void eval_uniform_tile(const double* __restrict__ x, const double* __restrict__ y,
-                                  const double* __restrict__ ypp, int64_t n, int64_t m, int64_t k0,
-                                  void* __restrict__ out, EvalSmem<BLOCK, QPT>& sm, int tid) {
-    using S = EvalSmem<BLOCK, QPT>;
-    const int64_t klast = min(m, k0 + (int64_t)S::kQ) - 1;
-    const double x0 = x[0];
-    const double xl = x[n - 1];
-    const double h = uniform_step(x0, xl, m);
-    tile_window(x, n, uniform_query(x0, xl, h, m, k0), uniform_query(x0, xl, h, m, klast), sm.win, tid);
-    __syncthreads();
-    const int64_t ilo = sm.win[0];
-    const int64_t ihi = max(sm.win[1], ilo);
-    const int64_t span = ihi - ilo;  // candidate knots ilo+1 .. ihi
-    if (span + 2 <= S::kWin) {
-        const int W = (int)span + 2;
-        for (int t = tid; t < W; t += BLOCK) {
-            sm.sx[t] = x[ilo + t];
-            if constexpr (MODE == kModeValue) {
-                sm.sy[t] = y[ilo + t];
-                sm.sp[t] = ypp[ilo + t];
-            }
-        }
-        __syncthreads();
-        if constexpr (MODE == kModeValue) {
-            for (int t = tid; t < W - 1; t += BLOCK) sm.sinv[t] = 1.0 / (sm.sx[t + 1] - sm.sx[t]);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int r = 0; r < QPT; ++r) {
-            const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-            if (k <= klast) {
-                const double q = uniform_query(x0, xl, h, m, k);
-                const int li = (int)lower_bound_idx(sm.sx, 1, span, q) - 1;
-                if constexpr (MODE == kModeValue) {
-                    const double v = newint(q, sm.sx[li], sm.sx[li + 1], sm.sy[li], sm.sy[li + 1], sm.sp[li],
-                                            sm.sp[li + 1], sm.sinv[li]);
-                    if constexpr (NT_STORE) __builtin_nontemporal_store(v, (double*)out + k);
-                    else ((double*)out)[k] = v;
-                } else if constexpr (MODE == kModeIndex) {
-                    ((int32_t*)out)[k] = (int32_t)(ilo + li);
-                } else {
-                    ((double*)out)[k] = (double)(ilo + li);
-                }
-            }
-        }
+// Query k0 + loc with k0 held exactly as a double (k0 + loc < 2^53 is exact),
+// so that the position equals uniform_query(.., k0 + loc) bit for bit.
+__device__ __forceinline__ double uniform_query_at(double x0, double xl, double h, int64_t m, double kd0,
+                                                   int64_t k, int64_t loc) {
+#pragma clang fp contract(off)
+    double kk = kd0 + (double)loc;
+    double step = kk * h;
+    double q = x0 + step;
+    q = (k >= m - 1) ? xl : q;
+    q = (k <= 0) ? x0 : q;
+    return q;
+}
+
+template <int MODE, bool NT_STORE>
+__device__ __forceinline__ void put_result(void* __restrict__ out, int64_t k, double v, int64_t i) {
+    if constexpr (MODE == kModeValue) {
+        if constexpr (NT_STORE) __builtin_nontemporal_store(v, (double*)out + k);
+        else ((double*)out)[k] = v;
+    } else if constexpr (MODE == kModeIndex) {
+        ((int32_t*)out)[k] = (int32_t)i;
     } else {
-        // Window wider than the LDS (knots much denser than queries): search
-        // the knot array in global memory, restricted to the tile's range.
-#pragma unroll
-        for (int r = 0; r < QPT; ++r) {
-            const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-            if (k <= klast) {
-                const double q = uniform_query(x0, xl, h, m, k);
-                const int64_t i = lower_bound_idx(x, ilo + 1, span, q) - 1;
-                if constexpr (MODE == kModeValue) {
-                    const double a = x[i], b = x[i + 1];
-                    const double v = newint(q, a, b, y[i], y[i + 1], ypp[i], ypp[i + 1], 1.0 / (b - a));
-                    if constexpr (NT_STORE) __builtin_nontemporal_store(v, (double*)out + k);
-                    else ((double*)out)[k] = v;
-                } else if constexpr (MODE == kModeIndex) {
-                    ((int32_t*)out)[k] = (int32_t)i;
-                } else {
-                    ((double*)out)[k] = (double)i;
-                }
+        ((double*)out)[k] = (double)i;
+    }
+}
+
+// One interval staged for evaluation: its ends a < b, values u, v, second
+// derivatives up, vp, and the per-interval constants 1/(b-a) and (b-a)^2 of
+// newint, computed once per interval instead of once per query.
+struct alignas(16) Interval {
+    double a, b, u, v, up, vp, inv, ba2;
+};
+
+// newint with the per-interval constants supplied.
+__device__ __forceinline__ double newint_rec(double q, const Interval& r) {
+    const double xa = q - r.a;
+    const double bx = r.b - q;
+    const double lower = xa * r.v + bx * r.u;
+    const double C = (xa * xa - r.ba2) * xa * r.vp;
+    const double D = (bx * bx - r.ba2) * bx * r.up;
+    return (lower + (1.0 / 6.0) * (C + D)) * r.inv;
+}
+
+template <int BLOCK, int QPT, int WIN>
+struct UniSmem {
+    static constexpr int kQ = BLOCK * QPT;
+    static constexpr int kWin = WIN;  // knots of a window the LDS holds
+    double sx[WIN];
+    Interval rec[WIN];
+    int64_t win[2];
+};
+
+template <int MODE>
+__device__ __forceinline__ void stage_window(const double* __restrict__ x, const double* __restrict__ y,
+                                             const double* __restrict__ ypp, int64_t g0, int W, double* sx,
+                                             Interval* rec, int tid, int block) {
+    for (int t = tid; t < W; t += block) {
+        const double a = x[g0 + t];
+        sx[t] = a;
+        if constexpr (MODE == kModeValue) {
+            if (t + 1 < W) {
+                Interval r;
+                r.a = a;
+                r.b = x[g0 + t + 1];
+                r.u = y[g0 + t];
+                r.v = y[g0 + t + 1];
+                r.up = ypp[g0 + t];
+                r.vp = ypp[g0 + t + 1];
+                const double ba = r.b - r.a;
+                r.inv = 1.0 / ba;
+                r.ba2 = ba * ba;
+                rec[t] = r;
             }
         }
     }
+}
+
+// Queries loc = r*BLOCK + tid of one tile, bracketed among the staged knots
+// [lia, lib] (local indices; base = global index of slot 0).
+template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE, bool LAST>
+__device__ __forceinline__ void tile_queries_lds(const UniSmem<BLOCK, QPT, WIN>& sm, double x0, double xl,
+                                                 double h, int64_t m, int64_t k0, int64_t klast, int64_t base,
+                                                 int lia, int lib, void* __restrict__ out, int tid) {
+    const double kd0 = (double)k0;
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int loc = r * BLOCK + tid;
+        const int64_t k = k0 + loc;
+        if (k <= klast) {
+            double q;
+            {
+#pragma clang fp contract(off)
+                const double step = (kd0 + (double)loc) * h;
+                q = x0 + step;
+            }
+            if constexpr (LAST) q = (k == m - 1 && k > 0) ? xl : q;  // m == 1: the only query is x[0]
+            const int li = (int)lower_bound_idx(sm.sx, lia + 1, lib - lia, q) - 1;
+            double v = 0.0;
+            if constexpr (MODE == kModeValue) v = newint_rec(q, sm.rec[li]);
+            put_result<MODE, NT_STORE>(out, k, v, base + li);
+        }
+    }
+}
+
+// Uniform queries of one tile.  Fast path: the knots are assumed to sit
+// roughly in proportion to their index, so the WIN knots around the tile's
+// proportional position are staged in the same load round as x[0] and
+// x[n-1]; a check on the first and last staged knot proves the guess covers
+// the tile (else ballot searches over the whole array run).  The tile's own
+// interval range is found once, so each query searches only the few
+// intervals its tile spans.
+template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE>
+__device__ void eval_uniform_tile(const double* __restrict__ x, const double* __restrict__ y,
+                                  const double* __restrict__ ypp, int64_t n, int64_t m, int64_t k0,
+                                  void* __restrict__ out, UniSmem<BLOCK, QPT, WIN>& sm, int tid) {
+    using S = UniSmem<BLOCK, QPT, WIN>;
+    const int64_t klast = min(m, k0 + (int64_t)S::kQ) - 1;
+    const int64_t W = min((int64_t)WIN, n);
+    int64_t g0;
+    {
+        const double kmid = 0.5 * ((double)k0 + (double)klast);
+        const double f = kmid * ((double)(n - 1) / (double)(m > 1 ? m - 1 : 1));
+        double c = f - 0.5 * (double)(W - 1);
+        c = fmin(fmax(c, 0.0), (double)(n - W));
+        g0 = (int64_t)c;
+    }
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    stage_window<MODE>(x, y, ypp, g0, (int)W, sm.sx, sm.rec, tid, BLOCK);
+    const double h = uniform_step(x0, xl, m);
+    const double qa = uniform_query(x0, xl, h, m, k0);
+    const double qb = uniform_query(x0, xl, h, m, klast);
+    __syncthreads();
+    const bool covers = (g0 == 0 || sm.sx[0] < qa) && (g0 + W == n || sm.sx[W - 1] >= qb);
+    int64_t base;
+    int lia, lib;
+    bool staged = true;
+    if (covers) {
+        base = g0;
+        if (tid == 0 || tid == kWave) {
+            const double q = tid == 0 ? qa : qb;
+            const int64_t c = lower_bound_idx(sm.sx, 0, W, q);  // staged knots below q
+            sm.win[tid == 0 ? 0 : 1] = clip_interval(g0 + c, n) - g0;
+        }
+        __syncthreads();
+        lia = (int)sm.win[0];
+        lib = (int)max(sm.win[1], sm.win[0]);
+    } else {
+        __syncthreads();  // every lane has read the guessed window
+        tile_window(x, n, qa, qb, sm.win, tid);
+        __syncthreads();
+        const int64_t ilo = sm.win[0];
+        const int64_t ihi = max(sm.win[1], ilo);
+        base = ilo;
+        staged = ihi - ilo + 2 <= WIN;
+        lia = 0;
+        lib = staged ? (int)(ihi - ilo) : 0;
+        if (staged) {
+            stage_window<MODE>(x, y, ypp, ilo, lib + 2, sm.sx, sm.rec, tid, BLOCK);
+            __syncthreads();
+        } else {
+            // Window wider than the LDS (knots much denser than queries):
+            // search the knot array in global memory within the tile's range.
+            const double kd0 = (double)k0;
+#pragma unroll
+            for (int r = 0; r < QPT; ++r) {
+                const int loc = r * BLOCK + tid;
+                const int64_t k = k0 + loc;
+                if (k <= klast) {
+                    const double q = uniform_query_at(x0, xl, h, m, kd0, k, loc);
+                    const int64_t i = lower_bound_idx(x, ilo + 1, ihi - ilo, q) - 1;
+                    double v = 0.0;
+                    if constexpr (MODE == kModeValue) {
+                        const double a = x[i], b = x[i + 1];
+                        v = newint(q, a, b, y[i], y[i + 1], ypp[i], ypp[i + 1], 1.0 / (b - a));
+                    }
+                    put_result<MODE, NT_STORE>(out, k, v, i);
+                }
+            }
+            return;
+        }
+    }
+    if (klast == m - 1)
+        tile_queries_lds<BLOCK, QPT, WIN, MODE, NT_STORE, true>(sm, x0, xl, h, m, k0, klast, base, lia, lib, out, tid);
+    else
+        tile_queries_lds<BLOCK, QPT, WIN, MODE, NT_STORE, false>(sm, x0, xl, h, m, k0, klast, base, lia, lib, out,
+                                                                tid);
 }
 
 // Explicit queries in any order: the tile's window spans the bracket of its
@@ -518,9 +816,9 @@ template <int BLOCK, int QPT>
 __device__ void eval_points_tile(const double* __restrict__ x, const double* __restrict__ y,
                                  const double* __restrict__ ypp, int64_t n, const double* __restrict__ xq,
                                  int64_t m, int64_t k0, double* __restrict__ yq, double* __restrict__ d1,
-                                 double* __restrict__ d2, int32_t* __restrict__ idx, EvalSmem<BLOCK, QPT>& sm,
-                                 double* red, int tid) {
-    using S = EvalSmem<BLOCK, QPT>;
+                                 double* __restrict__ d2, int32_t* __restrict__ idx,
+                                 EvalSmem<BLOCK, QPT, BLOCK * QPT + 2>& sm, double* red, int tid) {
+    using S = EvalSmem<BLOCK, QPT, BLOCK * QPT + 2>;
     constexpr int NW = BLOCK / kWave;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;

@@ -205,3 +205,91 @@ def test_eval_points_matches_oracle(kind):
     assert_close(host(d2)[ok], o_d2[ok], "d2 points " + kind, rtol=1e-9)
     if not ok.all():
         assert np.all(np.isnan(host(yq)[~ok]))
+
+
+SOLVE_CASES = [(3, 5), (13, 2048), (100, 7), (513, 100000), (1024, 1), (1025, 4096), (4097, 333),
+               (13000, 2048000), (20000, 20000), (65536, 1 << 20), (300000, 1000), (250, 3000000)]
+
+
+@pytest.mark.parametrize("n,m", SOLVE_CASES)
+@pytest.mark.parametrize("bc", [0, 1, 2, 3])
+def test_solve_uniform_matches_oracle(n, m, bc):
+    name, sd, ed = BCS[bc]
+    x, y = w.paper_curve(np.random.default_rng(3 * n + bc), n)
+    xd, yd = dev(x), dev(y)
+    ypp = torch.full_like(xd, np.nan)
+    yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    api.spline_solve_uniform(xd, yd, sd, ed, m, yq, ypp, st)
+    o_yq, o_ypp = oracle.spline_uniform(x, y, sd, ed, m)
+    assert int(host(st)[0]) == api.OK
+    assert_close(host(ypp), o_ypp, "solve ypp n=%d %s" % (n, name))
+    assert_close(host(yq), o_yq, "solve yq n=%d m=%d %s" % (n, m, name))
+
+
+def test_solve_uniform_halo_worst_case_decay():
+    # Widths shrinking by 1e-3 per knot make the forward error factor
+    # a/(b - a c') approach its 2/3 bound; the halo must still be enough.
+    n = 2000
+    w_ = np.empty(n - 1)
+    w_[0::2] = 1.0
+    w_[1::2] = 1e-3
+    x = np.concatenate([[0.0], np.cumsum(w_)])
+    y = np.random.default_rng(5).standard_normal(n) * 1e3
+    for m in (n * 64, 3000):
+        xd, yd = dev(x), dev(y)
+        ypp = torch.empty_like(xd)
+        yq = torch.empty(m, dtype=torch.float64, device="cuda")
+        api.spline_solve_uniform(xd, yd, -1.0, 1.0, m, yq, ypp)
+        o_yq, o_ypp = oracle.spline_uniform(x, y, -1.0, 1.0, m)
+        assert_close(host(ypp), o_ypp, "decay ypp")
+        assert_close(host(yq), o_yq, "decay yq")
+
+
+def test_solve_uniform_bad_knots_and_reuse():
+    x, y = w.paper_curve(np.random.default_rng(21), 9000)
+    xb = x.copy()
+    xb[7000] = xb[6999]
+    m = 300000
+    o_yq, o_ypp = oracle.spline_uniform(x, y, -1.0, 1.0, m)
+    for rep in range(3):
+        for xx, good in ((x, True), (xb, False)):
+            xd, yd = dev(xx), dev(y)
+            ypp = torch.full_like(xd, 7.0)
+            yq = torch.full((m,), 7.0, dtype=torch.float64, device="cuda")
+            st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+            api.spline_solve_uniform(xd, yd, -1.0, 1.0, m, yq, ypp, st)
+            if good:
+                assert int(host(st)[0]) == api.OK
+                assert_close(host(ypp), o_ypp, "reuse ypp")
+                assert_close(host(yq), o_yq, "reuse yq")
+            else:
+                assert int(host(st)[0]) == api.E_ORDER
+
+
+def test_solve_uniform_equals_two_launch_path():
+    inst = w.config_large(seed=2, bc=1)
+    xd, yd = dev(inst.x), dev(inst.y)
+    ypp1 = torch.empty_like(xd)
+    yq1 = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    api.spline_solve_uniform(xd, yd, inst.start_deriv, inst.end_deriv, inst.m, yq1, ypp1)
+    ypp2 = torch.empty_like(xd)
+    yq2 = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    api.spline_build(xd, yd, inst.start_deriv, inst.end_deriv, ypp2)
+    api.spline_eval_uniform(xd, yd, ypp2, inst.m, yq2)
+    assert_close(host(ypp1), host(ypp2), "one launch vs two", rtol=1e-12)
+    assert_close(host(yq1), host(yq2), "one launch vs two", rtol=1e-12)
+
+
+def test_solve_uniform_deterministic():
+    inst = w.config_large(seed=3, bc=2)
+    xd, yd = dev(inst.x), dev(inst.y)
+    outs = []
+    for _ in range(3):
+        ypp = torch.empty_like(xd)
+        yq = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+        api.spline_solve_uniform(xd, yd, inst.start_deriv, inst.end_deriv, inst.m, yq, ypp)
+        outs.append((host(ypp), host(yq)))
+    for ypp_k, yq_k in outs[1:]:
+        np.testing.assert_array_equal(ypp_k, outs[0][0])
+        np.testing.assert_array_equal(yq_k, outs[0][1])
