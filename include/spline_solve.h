@@ -211,7 +211,7 @@ typedef struct spline_plan spline_plan;
 /* Tuning knobs of a plan (0 = library default / autotuned choice). */
 typedef struct {
     int32_t block;            /* threads per workgroup of the fused kernel: 256 or 512  */
-    int32_t queries_per_tile; /* uniform queries per evaluate tile (block * 1..16)       */
+    int32_t queries_per_tile; /* most uniform queries per evaluate slice                  */
     int32_t grid_per_cu;      /* persistent workgroups per compute unit (1..8)           */
     int32_t fused;            /* 1: one persistent launch; 0: build + evaluate launches  */
 } spline_tuning;

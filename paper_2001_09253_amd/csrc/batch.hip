@@ -18,7 +18,7 @@
 namespace spl {
 
 constexpr int kSpinLimit = 1 << 25;  // ~ seconds of s_sleep before a tile gives up waiting
-constexpr int kBatchWin = 256;       // staged knot window of an evaluate tile
+constexpr int kBatchWin = kBatchWindow;  // staged knot window of an evaluate slice
 
 template <int BLOCK, int QPT>
 struct FusedSmem {
@@ -79,9 +79,8 @@ __device__ void run_tile(const BatchDevArgs& a, const TileItem& ti, FusedSmem<BL
     const int64_t n = a.koff[i + 1] - o;
     const int64_t qo = a.qoff[i];
     const int64_t m = a.qoff[i + 1] - qo;
-    eval_uniform_tile<BLOCK, QPT, kBatchWin, kModeValue, false>(a.x + o, a.y + o, a.ypp + o, n, m,
-                                                     (int64_t)ti.local * (BLOCK * QPT), a.yq + qo, sm.ev,
-                                                     threadIdx.x);
+    eval_uniform_range<BLOCK, QPT, kBatchWin, kModeValue, false>(a.x + o, a.y + o, a.ypp + o, n, m, ti.k0, ti.k1,
+                                                                 a.yq + qo, sm.ev, threadIdx.x);
 }
 
 template <int BLOCK, int QPT>
@@ -146,19 +145,15 @@ static int launch_variant(const BatchDevArgs& a, int fused, int grid, int64_t co
 spline_tuning default_tuning() {
     spline_tuning t;
     t.block = 256;
-    t.queries_per_tile = 1024;
+    t.queries_per_tile = 8192;
     t.grid_per_cu = 4;
-    t.fused = 1;
+    t.fused = 0;
     return t;
 }
 
-// The (block, queries per tile) pairs that are compiled.
-static bool compiled_shape(int block, int q) {
-    return (block == 256 && (q == 512 || q == 1024 || q == 2048)) || (block == 512 && (q == 1024 || q == 2048));
-}
-
 bool valid_tuning(const spline_tuning& t) {
-    return compiled_shape(t.block, t.queries_per_tile) && t.grid_per_cu >= 1 && t.grid_per_cu <= 8 &&
+    return (t.block == 256 || t.block == 512) && t.queries_per_tile >= t.block &&
+           t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 1 && t.grid_per_cu <= 8 &&
            (t.fused == 0 || t.fused == 1);
 }
 
@@ -212,10 +207,17 @@ void Batch::make_tables() {
         }
     }
     if (fill) items_.push_back(cur);
-    const int64_t Q = tuning_.queries_per_tile;
+    const int64_t cap = tuning_.queries_per_tile;
     for (int64_t i = 0; i < count_; ++i) {
-        const int64_t nt = uniform_[i] ? (m_[i] + Q - 1) / Q : 0;
-        for (int64_t t = 0; t < nt; ++t) tiles_.push_back(TileItem{(int32_t)i, (int32_t)t});
+        if (!uniform_[i]) continue;
+        // about 0.45 * window intervals per slice keeps the guessed window
+        // covering it; a slice is never below one workgroup's worth
+        const double per_interval = (double)m_[i] / (double)(n_[i] - 1);
+        int64_t sz = (int64_t)(0.45 * kBatchWindow * per_interval);
+        sz = std::min<int64_t>(sz, cap);
+        sz = std::max<int64_t>(sz, tuning_.block);
+        for (int64_t k = 0; k < m_[i]; k += sz)
+            tiles_.push_back(TileItem{(int32_t)i, 0, k, std::min<int64_t>(m_[i], k + sz)});
     }
 }
 
@@ -234,7 +236,6 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
         m_[i] = qoff[i + 1] - qoff[i];
         if (uniform) uniform_[i] = uniform[i] ? 1 : 0;
         if (n_[i] < 3 || n_[i] > SOLVE_MAX_N_BATCH || m_[i] < (uniform_[i] ? 1 : 0)) return SOLVE_E_SIZE;
-        if ((m_[i] + t.queries_per_tile - 1) / t.queries_per_tile > 0x7fffffffLL) return SOLVE_E_SIZE;
     }
     count_ = count;
     total_n_ = koff[count];
@@ -306,16 +307,9 @@ int Batch::launch(const double* x, const double* y, const double* sd, const doub
     a.n_tiles = (int32_t)tiles_.size();
     a.precision = (int32_t)precision_;
     const int grid = std::max(1, num_cu_ * tuning_.grid_per_cu);
-    const int q = tuning_.queries_per_tile;
     const int f = tuning_.fused;
-    if (tuning_.block == 256) {
-        if (q == 512) return launch_variant<256, 2>(a, f, grid, count_, s);
-        if (q == 1024) return launch_variant<256, 4>(a, f, grid, count_, s);
-        if (q == 2048) return launch_variant<256, 8>(a, f, grid, count_, s);
-    } else if (tuning_.block == 512) {
-        if (q == 1024) return launch_variant<512, 2>(a, f, grid, count_, s);
-        if (q == 2048) return launch_variant<512, 4>(a, f, grid, count_, s);
-    }
+    if (tuning_.block == 256) return launch_variant<256, 8>(a, f, grid, count_, s);
+    if (tuning_.block == 512) return launch_variant<512, 4>(a, f, grid, count_, s);
     return SOLVE_E_ARG;
 }
 
@@ -521,10 +515,11 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
         }
     }
     std::vector<spline_tuning> cands;
-    const int shapes[][2] = {{256, 512}, {256, 1024}, {256, 2048}, {512, 1024}, {512, 2048}};
-    for (const auto& sh : shapes) {
-        for (int gpc : {2, 4, 8}) cands.push_back(spline_tuning{sh[0], sh[1], gpc, 1});
-        cands.push_back(spline_tuning{sh[0], sh[1], 4, 0});
+    for (int block : {256, 512}) {
+        for (int cap : {2048, 4096, 8192, 16384}) {
+            for (int gpc : {2, 4, 8}) cands.push_back(spline_tuning{block, cap, gpc, 1});
+            cands.push_back(spline_tuning{block, cap, 4, 0});
+        }
     }
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;

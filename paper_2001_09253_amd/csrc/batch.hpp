@@ -4,7 +4,10 @@
 //   * build items: either one small curve per wavefront of the workgroup
 //     (n <= 64*8), or one larger curve built by the whole workgroup
 //     (n <= SOLVE_MAX_N_BATCH);
-//   * evaluate tiles: (curve, tile) pairs of queries_per_tile uniform queries.
+//   * evaluate slices: (curve, query range) pairs; a curve's queries are cut
+//     into slices of at most queries_per_tile, fewer when its knots are
+//     sparse relative to its queries (so that a slice's knots fit the staged
+//     window), and never below one workgroup's worth.
 // The fused kernel is persistent: each workgroup first claims build items
 // with an atomic counter until none are left, then walks the tile list with a
 // grid stride.  A tile waits (bounded spin) for its curve's ready flag.  This
@@ -24,6 +27,7 @@ namespace spl {
 
 constexpr int kItemLanes = 8;           // curves per packed build item (one per wavefront)
 constexpr int kWaveBuildMaxN = 64 * 8;   // largest curve one wavefront builds
+constexpr int kBatchWindow = 256;         // knots an evaluate slice stages
 constexpr int32_t kItemPacked = 0;
 constexpr int32_t kItemWhole = 1;
 
@@ -32,9 +36,11 @@ struct BuildItem {
     int32_t inst[kItemLanes];   // kItemWhole: inst[0] is built by the whole workgroup
 };
 
-struct TileItem {
+struct TileItem {  // uniform queries k0 .. k1-1 of curve inst
     int32_t inst;
-    int32_t local;  // tile index inside the curve
+    int32_t pad;
+    int64_t k0;
+    int64_t k1;
 };
 
 struct BatchDevArgs {

@@ -34,33 +34,6 @@ namespace spl {
 constexpr int kSolveBlock = 256;
 constexpr int kHalo = 128;
 
-// First uniform query strictly above v, in [0, m].  The positions are
-// non-decreasing in k, so k = floor((v - x0)/h) + 1 is right to within the
-// rounding of the positions; it is checked against the exact positions and
-// moved by single steps (a binary search covers anything further off).
-__device__ __forceinline__ int64_t first_query_above(double x0, double xl, double h, int64_t m, double v) {
-    double t = (m > 1) ? (v - x0) / h : 0.0;
-    t = fmin(fmax(t, -1.0), (double)m);  // also maps NaN to -1
-    int64_t k = (int64_t)floor(t) + 1;
-    k = k < 0 ? 0 : (k > m ? m : k);
-    for (int it = 0; it < 4; ++it) {
-        if (k > 0 && uniform_query(x0, xl, h, m, k - 1) > v) {
-            --k;
-        } else if (k < m && !(uniform_query(x0, xl, h, m, k) > v)) {
-            ++k;
-        } else {
-            return k;
-        }
-    }
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (uniform_query(x0, xl, h, m, mid) > v) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
 template <int BK>
 struct BlockSolve {
     static constexpr int kSpan = BK + 1 + 2 * kHalo;                         // rows of one local solve
@@ -88,8 +61,6 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
     __shared__ Fwd lds_f[kSolveBlock / kWave];
     __shared__ Bwd lds_b[kSolveBlock / kWave];
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wid = tid / kWave;
     const int ni = (int)n;
     const double x0 = x[0];
     const double xl = x[n - 1];
@@ -131,27 +102,8 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
         }
         __syncthreads();
         if constexpr (DENSE) {
-            if (tid == 0) {
-                int32_t acc = 0;
-                for (int t = 0; t < nb; ++t) {
-                    kc[t] = acc;
-                    const int64_t cnt = kq[t + 1] - kq[t];
-                    acc += (int32_t)(((cnt > 0 ? cnt : 0) + kWave - 1) / kWave);
-                }
-                kc[nb] = acc;
-            }
-            __syncthreads();
-            const int chunks = kc[nb];
-            int t = 0;
-            for (int c = wid; c < chunks; c += kSolveBlock / kWave) {
-                while (kc[t + 1] <= c) ++t;  // wave-uniform: chunks are visited in order
-                const int64_t kt = kq[t];
-                const int64_t k = kt + (int64_t)(c - kc[t]) * kWave + lane;
-                if (k < kq[t + 1]) {
-                    const double q = uniform_query(x0, xl, h, m, k);
-                    yq[k] = newint_rec(q, rec[t]);
-                }
-            }
+            block_chunk_prefix<kSolveBlock>(kq, kc, nb, tid);
+            dense_chunks<kSolveBlock / kWave, kModeValue, false>(kq, kc, rec, kx, nb, x0, xl, h, m, j0, yq, tid);
         } else {
             const int64_t ka = kq[0];
             const int64_t kz = kq[nb];

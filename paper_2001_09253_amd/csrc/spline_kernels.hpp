@@ -58,6 +58,33 @@ __device__ __forceinline__ double uniform_query(double x0, double xl, double h, 
     return q;
 }
 
+// First uniform query strictly above v, in [0, m].  The positions are
+// non-decreasing in k, so k = floor((v - x0)/h) + 1 is right to within the
+// rounding of the positions; it is checked against the exact positions and
+// moved by single steps (a binary search covers anything further off).
+__device__ __forceinline__ int64_t first_query_above(double x0, double xl, double h, int64_t m, double v) {
+    double t = (m > 1) ? (v - x0) / h : 0.0;
+    t = fmin(fmax(t, -1.0), (double)m);  // also maps NaN to -1
+    int64_t k = (int64_t)floor(t) + 1;
+    k = k < 0 ? 0 : (k > m ? m : k);
+    for (int it = 0; it < 4; ++it) {
+        if (k > 0 && uniform_query(x0, xl, h, m, k - 1) > v) {
+            --k;
+        } else if (k < m && !(uniform_query(x0, xl, h, m, k) > v)) {
+            ++k;
+        } else {
+            return k;
+        }
+    }
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (uniform_query(x0, xl, h, m, mid) > v) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
 // The rewritten interpolant of "Fast Interpolation" (newint) on [a, b] with
 // values u, v and second derivatives up, vp; inv_ba = 1/(b - a) is supplied by
 // the caller (computed once per interval).
@@ -670,6 +697,8 @@ struct UniSmem {
     static constexpr int kWin = WIN;  // knots of a window the LDS holds
     double sx[WIN];
     Interval rec[WIN];
+    int64_t kq[WIN + 1];  // dense tiles: first query of each touched interval
+    int32_t kc[WIN + 1];  // dense tiles: exclusive prefix of 64-query chunks
     int64_t win[2];
 };
 
@@ -698,46 +727,96 @@ __device__ __forceinline__ void stage_window(const double* __restrict__ x, const
     }
 }
 
-// Queries loc = r*BLOCK + tid of one tile, bracketed among the staged knots
-// [lia, lib] (local indices; base = global index of slot 0).
-template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE, bool LAST>
-__device__ __forceinline__ void tile_queries_lds(const UniSmem<BLOCK, QPT, WIN>& sm, double x0, double xl,
-                                                 double h, int64_t m, int64_t k0, int64_t klast, int64_t base,
-                                                 int lia, int lib, void* __restrict__ out, int tid) {
-    const double kd0 = (double)k0;
-#pragma unroll
-    for (int r = 0; r < QPT; ++r) {
-        const int loc = r * BLOCK + tid;
-        const int64_t k = k0 + loc;
-        if (k <= klast) {
-            double q;
-            {
+// Dense evaluation over nint consecutive intervals whose query ranges are
+// kq[t] .. kq[t+1]-1 and whose 64-query chunk offsets are kc[t] (kc[nint] =
+// total chunks): wavefront w takes chunks w, w + NW, ...; every lane of a
+// chunk is on the same interval, so no query searches.  Query k is
+// x0 + k*h computed as x0 + (kbase + lane)*h (both integers exact in
+// double), and the last query is x[n-1] itself.
+template <int NW, int MODE, bool NT_STORE>
+__device__ __forceinline__ void dense_chunks(const int64_t* kq, const int32_t* kc, const Interval* rec,
+                                             const double* sx, int nint, double x0, double xl, double h,
+                                             int64_t m, int64_t base, void* __restrict__ out, int tid) {
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const double dlane = (double)lane;
+    const int chunks = kc[nint];
+    int t = 0;
+    for (int c = wid; c < chunks; c += NW) {
+        while (kc[t + 1] <= c) ++t;  // wave-uniform; each wave visits its chunks in order
+        const int64_t kb = kq[t] + (int64_t)(c - kc[t]) * kWave;
+        const int64_t ke = kq[t + 1];
+        const int64_t k = kb + lane;
+        const double kbd = (double)kb;
+        double q;
+        {
 #pragma clang fp contract(off)
-                const double step = (kd0 + (double)loc) * h;
-                q = x0 + step;
-            }
-            if constexpr (LAST) q = (k == m - 1 && k > 0) ? xl : q;  // m == 1: the only query is x[0]
-            const int li = (int)lower_bound_idx(sm.sx, lia + 1, lib - lia, q) - 1;
+            const double step = (kbd + dlane) * h;
+            q = x0 + step;
+        }
+        if (ke == m) q = (k == m - 1 && k > 0) ? xl : q;
+        if (k < ke) {
             double v = 0.0;
-            if constexpr (MODE == kModeValue) v = newint_rec(q, sm.rec[li]);
-            put_result<MODE, NT_STORE>(out, k, v, base + li);
+            if constexpr (MODE == kModeValue) v = newint_rec(q, rec[t]);
+            put_result<MODE, NT_STORE>(out, k, v, base + t);
         }
     }
+    (void)sx;
 }
 
-// Uniform queries of one tile.  Fast path: the knots are assumed to sit
-// roughly in proportion to their index, so the WIN knots around the tile's
-// proportional position are staged in the same load round as x[0] and
-// x[n-1]; a check on the first and last staged knot proves the guess covers
-// the tile (else ballot searches over the whole array run).  The tile's own
-// interval range is found once, so each query searches only the few
-// intervals its tile spans.
+// Exclusive prefix sum of v over one wavefront (all lanes call); *total
+// receives the sum over the wave.
+__device__ __forceinline__ int32_t wave_excl_sum(int32_t v, int lane, int32_t* total) {
+    int32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    *total = __shfl(incl, kWave - 1);
+    return incl - v;
+}
+
+// kc[t] = exclusive prefix over t < nint of ceil((kq[t+1]-kq[t])/64), and
+// kc[nint] the total, by wave 0, 64 intervals at a time.  Ends with a
+// barrier.
+template <int BLOCK>
+__device__ __forceinline__ void block_chunk_prefix(const int64_t* kq, int32_t* kc, int nint, int tid) {
+    if (tid < kWave) {
+        const int lane = tid;
+        int32_t carry = 0;
+        for (int t0 = 0; t0 < nint; t0 += kWave) {
+            const int t = t0 + lane;
+            int32_t cnt = 0;
+            if (t < nint) {
+                const int64_t c = kq[t + 1] - kq[t];
+                cnt = (int32_t)(((c > 0 ? c : 0) + kWave - 1) / kWave);
+            }
+            int32_t tot;
+            const int32_t ex = wave_excl_sum(cnt, lane, &tot);
+            if (t < nint) kc[t] = carry + ex;
+            carry += tot;
+        }
+        if (lane == 0) kc[nint] = carry;
+    }
+    __syncthreads();
+}
+
+// Uniform queries k0 .. k1-1 of one curve.  Fast path: the knots are assumed
+// to sit roughly in proportion to their index, so the WIN knots around the
+// range's proportional position are staged in the same load round as x[0]
+// and x[n-1]; a check on the first and last staged knot proves the guess
+// covers the range (else ballot searches over the whole array run).  With at
+// least 4 queries per touched interval the range is dense: the first query of
+// every touched interval is found exactly, and each wavefront then takes
+// (interval, 64 queries) chunks, all lanes on one interval, with no search
+// per query.  Sparser ranges search the staged knots per query, and ranges
+// whose knots do not fit the window search the knot array in global memory.
 template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE>
-__device__ void eval_uniform_tile(const double* __restrict__ x, const double* __restrict__ y,
-                                  const double* __restrict__ ypp, int64_t n, int64_t m, int64_t k0,
-                                  void* __restrict__ out, UniSmem<BLOCK, QPT, WIN>& sm, int tid) {
-    using S = UniSmem<BLOCK, QPT, WIN>;
-    const int64_t klast = min(m, k0 + (int64_t)S::kQ) - 1;
+__device__ void eval_uniform_range(const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ ypp, int64_t n, int64_t m, int64_t k0, int64_t k1,
+                                   void* __restrict__ out, UniSmem<BLOCK, QPT, WIN>& sm, int tid) {
+    const int64_t klast = k1 - 1;
     const int64_t W = min((int64_t)WIN, n);
     int64_t g0;
     {
@@ -757,7 +836,6 @@ __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __
     const bool covers = (g0 == 0 || sm.sx[0] < qa) && (g0 + W == n || sm.sx[W - 1] >= qb);
     int64_t base;
     int lia, lib;
-    bool staged = true;
     if (covers) {
         base = g0;
         if (tid == 0 || tid == kWave) {
@@ -775,39 +853,64 @@ __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __
         const int64_t ilo = sm.win[0];
         const int64_t ihi = max(sm.win[1], ilo);
         base = ilo;
-        staged = ihi - ilo + 2 <= WIN;
-        lia = 0;
-        lib = staged ? (int)(ihi - ilo) : 0;
-        if (staged) {
-            stage_window<MODE>(x, y, ypp, ilo, lib + 2, sm.sx, sm.rec, tid, BLOCK);
-            __syncthreads();
-        } else {
+        if (ihi - ilo + 2 > WIN) {
             // Window wider than the LDS (knots much denser than queries):
-            // search the knot array in global memory within the tile's range.
+            // search the knot array in global memory within the range.
             const double kd0 = (double)k0;
-#pragma unroll
-            for (int r = 0; r < QPT; ++r) {
-                const int loc = r * BLOCK + tid;
+            for (int64_t loc = tid; k0 + loc <= klast; loc += BLOCK) {
                 const int64_t k = k0 + loc;
-                if (k <= klast) {
-                    const double q = uniform_query_at(x0, xl, h, m, kd0, k, loc);
-                    const int64_t i = lower_bound_idx(x, ilo + 1, ihi - ilo, q) - 1;
-                    double v = 0.0;
-                    if constexpr (MODE == kModeValue) {
-                        const double a = x[i], b = x[i + 1];
-                        v = newint(q, a, b, y[i], y[i + 1], ypp[i], ypp[i + 1], 1.0 / (b - a));
-                    }
-                    put_result<MODE, NT_STORE>(out, k, v, i);
+                const double q = uniform_query_at(x0, xl, h, m, kd0, k, loc);
+                const int64_t i = lower_bound_idx(x, ilo + 1, ihi - ilo, q) - 1;
+                double v = 0.0;
+                if constexpr (MODE == kModeValue) {
+                    const double a = x[i], b = x[i + 1];
+                    v = newint(q, a, b, y[i], y[i + 1], ypp[i], ypp[i + 1], 1.0 / (b - a));
                 }
+                put_result<MODE, NT_STORE>(out, k, v, i);
             }
             return;
         }
+        lia = 0;
+        lib = (int)(ihi - ilo);
+        stage_window<MODE>(x, y, ypp, ilo, lib + 2, sm.sx, sm.rec, tid, BLOCK);
+        __syncthreads();
     }
-    if (klast == m - 1)
-        tile_queries_lds<BLOCK, QPT, WIN, MODE, NT_STORE, true>(sm, x0, xl, h, m, k0, klast, base, lia, lib, out, tid);
-    else
-        tile_queries_lds<BLOCK, QPT, WIN, MODE, NT_STORE, false>(sm, x0, xl, h, m, k0, klast, base, lia, lib, out,
-                                                                tid);
+    const int span = lib - lia + 1;  // intervals the range touches
+    if (klast - k0 + 1 >= (int64_t)4 * span) {
+        for (int t = tid; t <= span; t += BLOCK) {
+            int64_t v;
+            if (t == 0) v = k0;
+            else if (t == span) v = k1;
+            else {
+                v = first_query_above(x0, xl, h, m, sm.sx[lia + t]);
+                v = v < k0 ? k0 : (v > k1 ? k1 : v);
+            }
+            sm.kq[t] = v;
+        }
+        __syncthreads();
+        block_chunk_prefix<BLOCK>(sm.kq, sm.kc, span, tid);
+        dense_chunks<BLOCK / kWave, MODE, NT_STORE>(sm.kq, sm.kc, sm.rec + lia, sm.sx + lia, span, x0, xl, h, m,
+                                                    base + lia, out, tid);
+        return;
+    }
+    const double kd0 = (double)k0;
+    for (int64_t loc = tid; k0 + loc <= klast; loc += BLOCK) {
+        const int64_t k = k0 + loc;
+        const double q = uniform_query_at(x0, xl, h, m, kd0, k, loc);
+        const int li = (int)lower_bound_idx(sm.sx, lia + 1, lib - lia, q) - 1;
+        double v = 0.0;
+        if constexpr (MODE == kModeValue) v = newint_rec(q, sm.rec[li]);
+        put_result<MODE, NT_STORE>(out, k, v, base + li);
+    }
+}
+
+// A tile of BLOCK*QPT consecutive uniform queries starting at k0.
+template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE>
+__device__ void eval_uniform_tile(const double* __restrict__ x, const double* __restrict__ y,
+                                  const double* __restrict__ ypp, int64_t n, int64_t m, int64_t k0,
+                                  void* __restrict__ out, UniSmem<BLOCK, QPT, WIN>& sm, int tid) {
+    const int64_t k1 = min(m, k0 + (int64_t)(BLOCK * QPT));
+    eval_uniform_range<BLOCK, QPT, WIN, MODE, NT_STORE>(x, y, ypp, n, m, k0, k1, out, sm, tid);
 }
 
 // Explicit queries in any order: the tile's window spans the bracket of its

@@ -14,7 +14,7 @@ from paper_2001_09253_amd import api, workloads as w
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(256, 512), (256, 1024), (256, 2048), (512, 1024), (512, 2048)]
+SHAPES = [(256, 256), (256, 2048), (256, 16384), (512, 512), (512, 8192)]
 
 
 def to_dev(b, status=True):
@@ -146,7 +146,7 @@ def test_autotune_picks_a_valid_tuning_and_caches(small_batch, small_batch_oracl
         path = os.path.join(d, "tune.json")
         best, ms = api.spline_plan_autotune(plan, bufs, reps=3, cache_path=path)
         assert ms > 0
-        assert (best.block, best.queries_per_tile) in SHAPES
+        assert best.block in (256, 512) and best.queries_per_tile >= best.block
         assert os.path.exists(path)
         got = api.spline_plan_get_tuning(plan)
         assert (got.block, got.queries_per_tile, got.grid_per_cu, got.fused) == \
