@@ -202,9 +202,9 @@ def bench_batched(args, precision):
                    "sizes": "log-uniform 0.1x..10x of (13, 2048)", "ends": "natural/flat/twist cycle", "seed": 0,
                    "tuning": {"block": best.block, "queries_per_tile": best.queries_per_tile,
                               "grid_per_cu": best.grid_per_cu, "fused": best.fused}},
-        "roofline": {"bound": "hbm", "kernel": "fused_batch" if best.fused else "build+eval",
+        "roofline": {"bound": "hbm", "kernel": "wave_items" if best.fused else "build+eval",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("fused_batch", wl),
+                     "traffic": measured_traffic("wave_items" if best.fused else "build+eval", wl),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": launch_ms},
     }
     if not args.no_cpu_baseline:
@@ -228,6 +228,81 @@ def bench_batched(args, precision):
     return out
 
 
+def bench_served(args):
+    """Poisson arrivals through the request API: continuous batching against
+    the plain one-request path, the same trace for both."""
+    import numpy as np
+
+    from paper_2001_09253_amd import api, serve, workloads
+
+    dur = args.served_seconds + 1.0
+    trace = workloads.poisson_trace(0, args.rate, dur, 0.1, 100.0)
+    reqs = serve.make_requests(trace, 1)
+    # one untimed pass through each path (library load, first launches)
+    short = workloads.Trace(trace.t[:64] - trace.t[0], trace.n[:64], trace.m[:64])
+    serve.replay(short, reqs[:64])
+    serve.replay(short, reqs[:64], plain=True)
+    res_b, _ = serve.replay(trace, reqs, warmup_s=1.0, budget=args.budget_gb << 30,
+                            flags=0 if args.served_graph else api.NO_GRAPH)
+    res_p, _ = serve.replay(trace, reqs, plain=True, warmup_s=1.0, budget=args.budget_gb << 30)
+    sb, sp = res_b.summary(), res_p.summary()
+    sel = trace.t >= 1.0
+    nsum = int(trace.n[sel].sum())
+    msum = int(trace.m[sel].sum())
+    bytes_alg = 24.0 * nsum + 8.0 * msum
+    gbs = bytes_alg / res_b.window_s / 1e9
+    out = {
+        "metric": METRIC, "value": sb["steps_per_s"], "unit": UNIT, "n_gpus": 1, "steps": res_b.requests,
+        "warmup": int((~sel).sum()), "ms_per_step": sb["mean_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "served: Poisson %.0f req/s for %.0f s after 1 s warm-up, sizes log-uniform "
+                               "0.1x..100x of (13, 2048), host result buffers" % (args.rate, args.served_seconds),
+                   "requests": res_b.requests, "sum_n": nsum, "sum_m": msum,
+                   "budget_bytes": args.budget_gb << 30, "graph": bool(args.served_graph)},
+        "latency_ms": {"served_p50": sb["p50_ms"], "served_p99": sb["p99_ms"], "plain_p50": sp["p50_ms"],
+                       "plain_p99": sp["p99_ms"], "served_max": sb["max_ms"], "plain_max": sp["max_ms"]},
+        "served": sb, "plain": sp,
+        "served_stats": res_b.stats,
+        "roofline": {"bound": "hbm", "kernel": "served batches (offered load)", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": None, "avg_launch_ms": None},
+    }
+    if args.sweep:
+        rows = []
+        for rate in (4000.0, 16000.0, 64000.0):
+            tr = workloads.poisson_trace(2, rate, 2.0, 0.1, 100.0)
+            rq = serve.make_requests(tr, 3)
+            rb, _ = serve.replay(tr, rq, warmup_s=0.5, flags=api.NO_GRAPH)
+            rp, _ = serve.replay(tr, rq, plain=True, warmup_s=0.5)
+            rows.append({"rate": rate, "served": rb.summary(), "plain": rp.summary()})
+        out["rate_sweep"] = rows
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle over the measured requests' inputs, OpenMP over
+        # requests, for a bounded share of the trace
+        idx = np.nonzero(sel)[0]
+        t0 = oracle.now()
+        done_steps = 0
+        used = 1
+        k = 0
+        while oracle.now() - t0 < args.cpu_seconds and k < len(idx):
+            chunk = idx[k:k + 256]
+            koff = np.concatenate([[0], np.cumsum([reqs[r].n for r in chunk])]).astype(np.int64)
+            qoff = np.concatenate([[0], np.cumsum([reqs[r].m for r in chunk])]).astype(np.int64)
+            xs = np.concatenate([reqs[r].x for r in chunk])
+            ys = np.concatenate([reqs[r].y for r in chunk])
+            sds = np.array([reqs[r].sd for r in chunk])
+            eds = np.array([reqs[r].ed for r in chunk])
+            _, _, _, used = oracle.batch_uniform(koff, qoff, xs, ys, sds, eds)
+            done_steps += int(koff[-1] + qoff[-1])
+            k += len(chunk)
+        t = oracle.now() - t0
+        out["cpu_baseline"] = {"value": done_steps / t, "unit": UNIT, "cores": used, "kind": "oracle",
+                               "sample": "first %d measured requests of the trace, back to back (no arrival "
+                                         "gaps), OpenMP over requests, %.1f s" % (k, t)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +312,11 @@ def main():
                     choices=["plain", "small", "plain2x", "batched", "mixed", "served"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
+    ap.add_argument("--served-seconds", type=float, default=10.0, help="served: measured seconds")
+    ap.add_argument("--budget-gb", type=int, default=200, help="served: HBM admission budget")
+    ap.add_argument("--served-graph", action="store_true", help="served: capture each batch as a hipGraph")
+    ap.add_argument("--sweep", action="store_true", help="served: also a short sweep of arrival rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: the spline path is measured on one MI355X "
@@ -252,7 +332,6 @@ def main():
         from paper_2001_09253_amd import api
         out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)
     else:
-        from bench_serving import bench_served
         out = bench_served(args)
     print(json.dumps(out))
 

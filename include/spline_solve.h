@@ -125,8 +125,10 @@ int solve_submit(solve_ctx *ctx, const double *knots, const double *values, int6
  * returns E_TICKET.  Errors: E_ARG, E_TICKET. */
 int solve_poll(solve_ctx *ctx, solve_ticket ticket, int *status);
 
-/* Blocking form of solve_poll: waits until the ticket is DONE or ERROR (or
- * timeout_ms elapses, < 0 = forever; then *status = SOLVE_PENDING). */
+/* Waits until the ticket is DONE or ERROR (or timeout_ms elapses, < 0 =
+ * forever; then *status = SOLVE_PENDING) and reports its status.  Does not
+ * reap the ticket: solve_ticket_info still works, and the solve_poll that
+ * reports it finished reaps it.  Errors: E_ARG, E_TICKET. */
 int solve_wait(solve_ctx *ctx, solve_ticket ticket, int *status, int64_t timeout_ms);
 
 /* Times of a completed or pending ticket in seconds on the library's
@@ -203,17 +205,31 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
                        int32_t *idx, void *stream);
 
 /* ============================================================================
- * Batched form: many curves in CSR layout in one persistent fused launch.
+ * Batched form: many curves in CSR layout, each solved ("Generating Second
+ * Derivatives") and evaluated at its own uniform queries ("Fast
+ * Interpolation"), in one launch.
+ *
+ * Every wavefront takes a work item (curve, knot block, share of the
+ * block's queries), solves the block's rows for y'' in its own LDS -- the
+ * whole curve when n <= 512 (n <= 256 when every curve of the batch is that
+ * small), else 255 intervals plus 128 halo rows on either side, whose dropped
+ * coupling is below 4.5 (2/3)^128 of max|y''| -- and evaluates its queries;
+ * wavefronts never wait on one another.
  * ========================================================================== */
 
 typedef struct spline_plan spline_plan;
 
-/* Tuning knobs of a plan (0 = library default / autotuned choice). */
+/* Tuning knobs of a plan: block = 64, 128 or 256 threads (1, 2 or 4
+ * independent wavefronts per workgroup); queries_per_tile = largest share of
+ * queries per work item (64 .. 2^24); grid_per_cu = 0 for one work item per
+ * wavefront (the hardware dispatcher balances), else at most that many
+ * persistent workgroups per compute unit (1..64) striding over the items;
+ * fused must be 1 (the single-launch kernel is the only form). */
 typedef struct {
-    int32_t block;            /* threads per workgroup of the fused kernel: 256 or 512  */
-    int32_t queries_per_tile; /* most uniform queries per evaluate slice                  */
-    int32_t grid_per_cu;      /* persistent workgroups per compute unit (1..8)           */
-    int32_t fused;            /* 1: one persistent launch; 0: build + evaluate launches  */
+    int32_t block;
+    int32_t queries_per_tile;
+    int32_t grid_per_cu;
+    int32_t fused;
 } spline_tuning;
 
 /* Plan a batch from host-side sizes: count instances, knot offsets koff[count+1]
@@ -221,8 +237,9 @@ typedef struct {
  * koff[i]..koff[i+1]-1 and outputs qoff[i]..qoff[i+1]-1).  Every n_i must be
  * in [3, SOLVE_MAX_N_BATCH] and every m_i >= 1.  precision: SOLVE_FP64 or
  * SOLVE_FP32_REFINE.  tuning: nullable (library defaults).  The plan owns a
- * device copy of the work table and scratch counters; *out must be released
- * with spline_plan_destroy.  Errors: E_ARG, E_SIZE, E_DEVICE. */
+ * device copy of its work tables; *out must be released with
+ * spline_plan_destroy.  Errors: E_ARG (also an invalid tuning), E_SIZE,
+ * E_DEVICE. */
 int spline_plan_create(int device, int64_t count, const int64_t *koff, const int64_t *qoff,
                        uint32_t precision, const spline_tuning *tuning, spline_plan **out);
 

@@ -1,5 +1,5 @@
-// Batched spline path: persistent fused kernel, its two-launch form, hipGraph
-// capture and the autotuner (C ABI: spline_plan_*).
+// Batched spline path: the single-launch wave-item kernel, hipGraph capture
+// and the autotuner (C ABI: spline_plan_*).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <numeric>
 #include <sstream>
 #include <string>
 
@@ -17,157 +18,214 @@
 
 namespace spl {
 
-constexpr int kSpinLimit = 1 << 25;  // ~ seconds of s_sleep before a tile gives up waiting
-constexpr int kBatchWin = kBatchWindow;  // staged knot window of an evaluate slice
-
-template <int BLOCK, int QPT>
-struct FusedSmem {
-    static constexpr int kNW = BLOCK / kWave;
-    static constexpr int kCHB = SOLVE_MAX_N_BATCH / BLOCK;  // rows per lane of a whole-group build
-    static constexpr int kBuildDoubles =
-        (BLOCK * kCHB > kNW * kWaveBuildMaxN) ? BLOCK * kCHB : kNW * kWaveBuildMaxN;
-    union {
-        UniSmem<BLOCK, QPT, kBatchWin> ev;
-        double build[kBuildDoubles];
-    };
-    Fwd lds_f[kNW];
-    Bwd lds_b[kNW];
-    int item;
+struct alignas(16) IntervalConst {  // 1/(b - a) and (b - a)^2 of one interval
+    double inv, ba2;
 };
 
-// Build one work item.  Every lane of the workgroup calls this.
-template <int BLOCK, int QPT>
-__device__ void run_build_item(const BatchDevArgs& a, const BuildItem& bi, FusedSmem<BLOCK, QPT>& sm,
-                               bool signal) {
-    using S = FusedSmem<BLOCK, QPT>;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wid = tid / kWave;
-    if (bi.kind == kItemWhole) {
-        const int i = bi.inst[0];
-        const int64_t o = a.koff[i];
-        const int n = (int)(a.koff[i + 1] - o);
-        build_group<BLOCK, S::kCHB, false>(a.x + o, a.y + o, n, a.sd[i], a.ed[i], a.ypp + o,
-                                           a.status ? a.status + i : nullptr, sm.build, sm.lds_f, sm.lds_b, tid);
-    } else {
-        const int i = wid < kItemLanes ? bi.inst[wid] : -1;
-        if (i >= 0) {
-            const int64_t o = a.koff[i];
-            const int n = (int)(a.koff[i + 1] - o);
-            build_group<kWave, kWaveBuildMaxN / kWave, true>(a.x + o, a.y + o, n, a.sd[i], a.ed[i], a.ypp + o,
-                                                             a.status ? a.status + i : nullptr,
-                                                             sm.build + wid * kWaveBuildMaxN, nullptr, nullptr,
-                                                             lane);
-        }
-    }
-    if (signal) {
-        // one release for the whole item, then its curves' ready flags
-        __syncthreads();
-        if (tid == 0) release_fence_agent();
-        __syncthreads();
-        if (tid < kItemLanes) {
-            const int i = bi.kind == kItemWhole ? (tid == 0 ? bi.inst[0] : -1) : bi.inst[tid];
-            if (i >= 0) __hip_atomic_store(&a.ready[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+// One wavefront's LDS: the span's knots, values and second derivatives (knot j
+// at [j - max(rs - 1, 0)], y'' of row j at so[j - rs]) and the constants of the
+// owned intervals (interval t at ib[t - j0]).
+template <int CH>
+struct WaveSmem {
+    static constexpr int kRows = kWave * CH;
+    double sx[kRows + 2];
+    double sy[kRows + 2];
+    double so[kRows + 2];
+    IntervalConst ib[kRows];
+};
+
+// Whether x[0..n) fails to increase strictly (or holds a NaN); every lane of
+// the wavefront gets the answer.
+__device__ __forceinline__ bool wave_unordered(const double* __restrict__ x, int n, int lane) {
+    bool bad = false;
+    for (int j = 1 + lane; j < n; j += kWave) bad |= !(x[j] > x[j - 1]);
+    return __ballot(bad) != 0ull;
 }
 
-template <int BLOCK, int QPT>
-__device__ void run_tile(const BatchDevArgs& a, const TileItem& ti, FusedSmem<BLOCK, QPT>& sm) {
-    const int i = ti.inst;
-    const int64_t o = a.koff[i];
-    const int64_t n = a.koff[i + 1] - o;
+// One wave item.  All 64 lanes of the wavefront call this.
+template <int CH>
+__device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem<CH>& sm, int lane) {
+    const int i = it.inst;
+    const int64_t ko = a.koff[i];
+    const int n = (int)(a.koff[i + 1] - ko);
     const int64_t qo = a.qoff[i];
     const int64_t m = a.qoff[i + 1] - qo;
-    eval_uniform_range<BLOCK, QPT, kBatchWin, kModeValue, false>(a.x + o, a.y + o, a.ypp + o, n, m, ti.k0, ti.k1,
-                                                                 a.yq + qo, sm.ev, threadIdx.x);
-}
-
-template <int BLOCK, int QPT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void fused_kernel(BatchDevArgs a) {
-    __shared__ FusedSmem<BLOCK, QPT> sm;
-    const int tid = threadIdx.x;
-    // Phase 1: claim build items until none are left.
-    for (;;) {
-        if (tid == 0) sm.item = atomicAdd(&a.counters[0], 1);
-        __syncthreads();
-        const int it = sm.item;
-        __syncthreads();
-        if (it >= a.n_items) break;
-        run_build_item<BLOCK, QPT>(a, a.items[it], sm, true);
-        __syncthreads();
+    const double* __restrict__ x = a.x + ko;
+    const double* __restrict__ y = a.y + ko;
+    const int j0 = it.j0;
+    const int j1 = it.j1;
+    const bool whole = j0 == 0 && j1 == n - 1;
+    const bool reporter = j0 == 0 && it.s == 0;  // writes the curve's status (and NaNs if it is bad)
+    // a1-a4: y'' over the span, exact for a whole curve and exact to rounding
+    // with the halo (the dropped coupling decays by 2/3 or better per row).
+    const int rs = whole ? 0 : max(0, j0 - kBatchHalo);
+    const int re = whole ? n : min(n, j1 + 1 + kBatchHalo);
+    bool bad = build_span<kWave, CH, true, SoloGroup, true>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr, nullptr,
+                                                             sm.sx, nullptr, nullptr, SoloGroup{}, lane, sm.sy,
+                                                             sm.so);
+    if (!whole) bad = bad || wave_unordered(x, n, lane);
+    if (bad) {
+        if (reporter) {
+            const double nan = __builtin_nan("");
+            if (a.ypp)
+                for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = nan;
+            if (it.S > 0)
+                for (int64_t k = lane; k < m; k += kWave) a.yq[qo + k] = nan;
+            if (a.status && lane == 0) a.status[i] = kStatusOrder;
+        }
+        return;
     }
-    // Phase 2: evaluate tiles with a grid stride, each after its curve is ready.
-    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-        const TileItem ti = a.tiles[t];
-        if (tid == 0) (void)wait_flag_at_least<2>(&a.ready[ti.inst], 1, kSpinLimit, &a.counters[1]);
-        __syncthreads();
-        run_tile<BLOCK, QPT>(a, ti, sm);
-        __syncthreads();
+    if (reporter && a.status && lane == 0) a.status[i] = kStatusOk;
+    const int lo = max(rs - 1, 0);
+    if (it.s == 0 && a.ypp) {
+        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+        for (int j = j0 + lane; j < jend; j += kWave) a.ypp[ko + j] = sm.so[j - rs];
+    }
+    if (it.S == 0) return;
+    for (int t = j0 + lane; t < j1; t += kWave) {
+        const double ba = sm.sx[t + 1 - lo] - sm.sx[t - lo];
+        sm.ib[t - j0] = IntervalConst{1.0 / ba, ba * ba};
+    }
+    wave_sync();
+
+    // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the
+    // first block); this item takes share s of S of them.
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    const double rh = (m > 1) ? 1.0 / h : 0.0;
+    const int64_t ka = (j0 == 0) ? 0 : first_query_above_r(x0, xl, h, rh, m, sm.sx[j0 - lo]);
+    const int64_t kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, sm.sx[j1 - lo]);
+    const int64_t len = kb - ka;
+    const int64_t per = len / it.S;
+    const int64_t rem = len % it.S;
+    const int64_t k0 = ka + per * it.s + min((int64_t)it.s, rem);
+    const int64_t k1 = k0 + per + ((int64_t)it.s < rem ? 1 : 0);
+    if (k0 >= k1) return;
+    double* __restrict__ out = a.yq + qo;
+
+    if (len < 4 * (int64_t)(j1 - j0)) {
+        // sparse: every query searches the block's knots
+        for (int64_t k = k0 + lane; k < k1; k += kWave) {
+            const double q = uniform_query(x0, xl, h, m, k);
+            const int t = (int)lower_bound_idx(sm.sx, j0 + 1 - lo, j1 - 1 - j0, q) + lo - 1;
+            const IntervalConst c = sm.ib[t - j0];
+            out[k] = newint(q, sm.sx[t - lo], sm.sx[t + 1 - lo], sm.sy[t - lo], sm.sy[t + 1 - lo],
+                            sm.so[t - rs], sm.so[t + 1 - rs], c.inv);
+        }
+        return;
+    }
+    // dense: 64 consecutive queries at a time; the wavefront carries the
+    // interval t of its next query and the first query knext of interval
+    // t + 1, and each lane moves past the boundaries its own query crossed.
+    int t = j0;
+    if (k0 > ka) {
+        // interval of query k0: j0 plus the interior knots of the block below it
+        const double q0 = uniform_query(x0, xl, h, m, k0);
+        int cnt = 0;
+        for (int j = j0 + 1 + lane; j - lane < j1; j += kWave)
+            cnt += __popcll(__ballot(j < j1 && sm.sx[j - lo] < q0));
+        t = j0 + cnt;
+    }
+    int64_t knext = (t + 1 < j1) ? first_query_above_r(x0, xl, h, rh, m, sm.sx[t + 1 - lo]) : k1;
+    const double dl = (double)lane;
+    for (int64_t kc = k0; kc < k1; kc += kWave) {
+        const int64_t k = kc + lane;
+        const int64_t klast = min(kc + kWave - 1, k1 - 1);
+        int tl = t;
+        while (knext <= klast) {
+            ++t;
+            tl = (k >= knext) ? t : tl;
+            knext = (t + 1 < j1) ? first_query_above_r(x0, xl, h, rh, m, sm.sx[t + 1 - lo]) : k1;
+        }
+        if (k < k1) {
+            double q;
+            {
+#pragma clang fp contract(off)
+                // (double)kc + lane is (double)k exactly: the position equals
+                // uniform_query(.., k) bit for bit
+                const double step = ((double)kc + dl) * h;
+                q = x0 + step;
+            }
+            q = (k >= m - 1) ? xl : q;
+            q = (k <= 0) ? x0 : q;
+            const IntervalConst c = sm.ib[tl - j0];
+            const double av = sm.sx[tl - lo];
+            const double bv = sm.sx[tl + 1 - lo];
+            // a6: newint with the interval's 1/(b - a) and (b - a)^2
+            const double xa = q - av;
+            const double bx = bv - q;
+            const double lower = xa * sm.sy[tl + 1 - lo] + bx * sm.sy[tl - lo];
+            const double C = (xa * xa - c.ba2) * xa * sm.so[tl + 1 - rs];
+            const double D = (bx * bx - c.ba2) * bx * sm.so[tl - rs];
+            out[k] = (lower + (1.0 / 6.0) * (C + D)) * c.inv;
+        }
     }
 }
 
-// Two-launch form: one workgroup per build item, then one per tile.
-template <int BLOCK, int QPT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void build_items_kernel(BatchDevArgs a) {
-    __shared__ FusedSmem<BLOCK, QPT> sm;
-    run_build_item<BLOCK, QPT>(a, a.items[blockIdx.x], sm, false);
+template <int CH, int WPG>
+__global__ __launch_bounds__(WPG * kWave) void wave_items_kernel(BatchDevArgs a) {
+    __shared__ WaveSmem<CH> smem[WPG];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int64_t stride = (int64_t)gridDim.x * WPG;
+    for (int64_t w = (int64_t)blockIdx.x * WPG + wid; w < a.n_witems; w += stride)
+        run_wave_item<CH>(a, a.witems[w], smem[wid], lane);
 }
 
-template <int BLOCK, int QPT>
-__global__ __launch_bounds__(BLOCK) void eval_tiles_kernel(BatchDevArgs a) {
-    __shared__ FusedSmem<BLOCK, QPT> sm;
-    run_tile<BLOCK, QPT>(a, a.tiles[blockIdx.x], sm);
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+static int wave_ch_for(int64_t max_n) {
+    if (max_n <= 64) return 1;
+    if (max_n <= 128) return 2;
+    if (max_n <= 192) return 3;
+    if (max_n <= 256) return 4;
+    return kWaveMaxCH;
 }
 
-// Clears the claim counter, the timeout flag and the ready flags (a kernel, so
-// that it can sit in a captured graph).
-__global__ void reset_kernel(int32_t* counters, int32_t* ready, int64_t count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 4) counters[i] = 0;
-    for (int64_t j = i; j < count; j += (int64_t)gridDim.x * blockDim.x) ready[j] = 0;
+template <int CH, int WPG>
+static int launch_waves(const BatchDevArgs& a, int grid_per_cu, int num_cu, hipStream_t s) {
+    const int64_t groups = (a.n_witems + WPG - 1) / WPG;
+    int64_t grid = groups;
+    if (grid_per_cu > 0) grid = std::min<int64_t>(groups, (int64_t)num_cu * grid_per_cu);
+    if (grid < 1) return SOLVE_OK;
+    wave_items_kernel<CH, WPG><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
+    return SOLVE_OK;
 }
 
-template <int BLOCK, int QPT>
-static int launch_variant(const BatchDevArgs& a, int fused, int grid, int64_t count, hipStream_t s) {
-    if (fused) {
-        const int rb = 256;
-        const int rg = (int)std::min<int64_t>(1024, (count + rb - 1) / rb + 1);
-        reset_kernel<<<rg, rb, 0, s>>>(a.counters, a.ready, count);
-        fused_kernel<BLOCK, QPT><<<grid, BLOCK, 0, s>>>(a);
-    } else {
-        if (a.n_items > 0) build_items_kernel<BLOCK, QPT><<<a.n_items, BLOCK, 0, s>>>(a);
-        if (a.n_tiles > 0) eval_tiles_kernel<BLOCK, QPT><<<a.n_tiles, BLOCK, 0, s>>>(a);
+template <int CH>
+static int launch_waves_ch(const BatchDevArgs& a, const spline_tuning& t, int num_cu, hipStream_t s) {
+    switch (t.block) {
+        case 64: return launch_waves<CH, 1>(a, t.grid_per_cu, num_cu, s);
+        case 128: return launch_waves<CH, 2>(a, t.grid_per_cu, num_cu, s);
+        case 256: return launch_waves<CH, 4>(a, t.grid_per_cu, num_cu, s);
+        default: return SOLVE_E_ARG;
     }
-    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
 spline_tuning default_tuning() {
     spline_tuning t;
     t.block = 256;
-    t.queries_per_tile = 8192;
-    t.grid_per_cu = 4;
-    t.fused = 0;
+    t.queries_per_tile = 4096;
+    t.grid_per_cu = 0;
+    t.fused = 1;
     return t;
 }
 
 bool valid_tuning(const spline_tuning& t) {
-    return (t.block == 256 || t.block == 512) && t.queries_per_tile >= t.block &&
-           t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 1 && t.grid_per_cu <= 8 &&
-           (t.fused == 0 || t.fused == 1);
+    return t.fused == 1 && (t.block == 64 || t.block == 128 || t.block == 256) && t.queries_per_tile >= 64 &&
+           t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
 }
 
-Batch::~Batch() {
-    hipFree(d_items_);
-    hipFree(d_tiles_);
-    hipFree(d_counters_);
-}
+Batch::~Batch() { (void)hipFree(d_tables_); }
 
 int Batch::ensure(void** p, size_t* cap, size_t bytes) {
     if (bytes <= *cap && *p) return SOLVE_OK;
     size_t want = std::max<size_t>(bytes, 256);
     want = std::max(want, *cap + *cap / 2);
-    if (*p) hipFree(*p);
+    if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
     if (hipMalloc(p, want) != hipSuccess) {
@@ -179,46 +237,39 @@ int Batch::ensure(void** p, size_t* cap, size_t bytes) {
 }
 
 void Batch::make_tables() {
-    const int nw = tuning_.block / kWave;
-    items_.clear();
-    tiles_.clear();
-    // Larger curves first: a whole workgroup each, claimed early.
-    for (int64_t i = 0; i < count_; ++i) {
-        if (n_[i] > kWaveBuildMaxN) {
-            BuildItem b;
-            b.kind = kItemWhole;
-            for (int w = 0; w < kItemLanes; ++w) b.inst[w] = -1;
-            b.inst[0] = (int32_t)i;
-            items_.push_back(b);
-        }
-    }
-    BuildItem cur;
-    int fill = 0;
-    for (int64_t i = 0; i < count_; ++i) {
-        if (n_[i] > kWaveBuildMaxN) continue;
-        if (fill == 0) {
-            cur.kind = kItemPacked;
-            for (int w = 0; w < kItemLanes; ++w) cur.inst[w] = -1;
-        }
-        cur.inst[fill++] = (int32_t)i;
-        if (fill == nw) {
-            items_.push_back(cur);
-            fill = 0;
-        }
-    }
-    if (fill) items_.push_back(cur);
+    // wave items: whole curves when they fit one wavefront's rows, else knot
+    // blocks with halos; shares of at most about queries_per_tile queries
+    witems_.clear();
+    const int rows = wave_ch_ * kWave;
     const int64_t cap = tuning_.queries_per_tile;
+    std::vector<double> cost;
     for (int64_t i = 0; i < count_; ++i) {
-        if (!uniform_[i]) continue;
-        // about 0.45 * window intervals per slice keeps the guessed window
-        // covering it; a slice is never below one workgroup's worth
-        const double per_interval = (double)m_[i] / (double)(n_[i] - 1);
-        int64_t sz = (int64_t)(0.45 * kBatchWindow * per_interval);
-        sz = std::min<int64_t>(sz, cap);
-        sz = std::max<int64_t>(sz, tuning_.block);
-        for (int64_t k = 0; k < m_[i]; k += sz)
-            tiles_.push_back(TileItem{(int32_t)i, 0, k, std::min<int64_t>(m_[i], k + sz)});
+        const int64_t n = n_[i];
+        const int bk = (n <= rows) ? (int)(n - 1) : kWaveBlock;
+        for (int64_t j0 = 0; j0 < n - 1; j0 += bk) {
+            const int64_t j1 = std::min<int64_t>(j0 + bk, n - 1);
+            const int64_t span = (n <= rows) ? n : std::min<int64_t>(n, j1 + 1 + kBatchHalo) -
+                                                       std::max<int64_t>(0, j0 - kBatchHalo);
+            int64_t S = 0;
+            double est = 0.0;
+            if (uniform_[i]) {
+                est = (double)m_[i] * (double)(j1 - j0) / (double)(n - 1);
+                S = std::max<int64_t>(1, (int64_t)std::ceil(est / (double)cap));
+            }
+            for (int64_t s = 0; s < std::max<int64_t>(S, 1); ++s) {
+                witems_.push_back(WaveItem{(int32_t)i, (int16_t)j0, (int16_t)j1, (int32_t)s, (int32_t)S});
+                // a row of the build costs about as much as 8 queries
+                cost.push_back(8.0 * (double)span + (S ? est / (double)S : 0.0));
+            }
+        }
     }
+    // decreasing work, so that the last wavefronts to start hold the least
+    std::vector<size_t> order(witems_.size());
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t p, size_t q) { return cost[p] > cost[q]; });
+    std::vector<WaveItem> sorted(witems_.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = witems_[order[k]];
+    witems_.swap(sorted);
 }
 
 int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const spline_tuning& t,
@@ -231,64 +282,55 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
     n_.assign(count, 0);
     m_.assign(count, 0);
     uniform_.assign(count, 1);
+    max_n_ = 0;
     for (int64_t i = 0; i < count; ++i) {
         n_[i] = koff[i + 1] - koff[i];
         m_[i] = qoff[i + 1] - qoff[i];
         if (uniform) uniform_[i] = uniform[i] ? 1 : 0;
         if (n_[i] < 3 || n_[i] > SOLVE_MAX_N_BATCH || m_[i] < (uniform_[i] ? 1 : 0)) return SOLVE_E_SIZE;
+        max_n_ = std::max(max_n_, n_[i]);
     }
     count_ = count;
     total_n_ = koff[count];
     total_m_ = qoff[count];
-    tuning_ = t;
     precision_ = precision;
-    make_tables();
-    if (tiles_.size() > 0x7fffffffULL || items_.size() > 0x7fffffffULL) return SOLVE_E_SIZE;
     if (!num_cu_) {
         if (hipDeviceGetAttribute(&num_cu_, hipDeviceAttributeMultiprocessorCount, device_) != hipSuccess)
             return SOLVE_E_DEVICE;
     }
-    int rc = ensure(&d_items_, &cap_items_, items_.size() * sizeof(BuildItem));
-    if (!rc) rc = ensure(&d_tiles_, &cap_tiles_, tiles_.size() * sizeof(TileItem));
-    if (!rc) rc = ensure(&d_counters_, &cap_counters_, (4 + (size_t)count) * sizeof(int32_t));
-    return rc;
+    return retile(t);
 }
 
 int Batch::retile(const spline_tuning& t) {
     if (!valid_tuning(t)) return SOLVE_E_ARG;
     tuning_ = t;
+    wave_ch_ = wave_ch_for(max_n_);
     make_tables();
-    int rc = ensure(&d_items_, &cap_items_, items_.size() * sizeof(BuildItem));
-    if (!rc) rc = ensure(&d_tiles_, &cap_tiles_, tiles_.size() * sizeof(TileItem));
-    return rc;
+    return ensure(&d_tables_, &cap_tables_, table_bytes());
+}
+
+size_t Batch::table_bytes() const { return witems_.size() * sizeof(WaveItem); }
+
+void Batch::write_tables(void* dst) const {
+    if (!witems_.empty()) std::memcpy(dst, witems_.data(), table_bytes());
 }
 
 int Batch::upload(hipStream_t s) {
-    if (!items_.empty() &&
-        hipMemcpyAsync(d_items_, items_.data(), items_.size() * sizeof(BuildItem), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-        return SOLVE_E_DEVICE;
-    if (!tiles_.empty() &&
-        hipMemcpyAsync(d_tiles_, tiles_.data(), tiles_.size() * sizeof(TileItem), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-        return SOLVE_E_DEVICE;
-    return SOLVE_OK;
-}
-
-int Batch::upload_staged(hipStream_t s, void* pinned) {
-    const size_t bi = items_.size() * sizeof(BuildItem);
-    const size_t bt = tiles_.size() * sizeof(TileItem);
-    if (bi) std::memcpy(pinned, items_.data(), bi);
-    if (bt) std::memcpy((char*)pinned + bi, tiles_.data(), bt);
-    if (bi && hipMemcpyAsync(d_items_, pinned, bi, hipMemcpyHostToDevice, s) != hipSuccess) return SOLVE_E_DEVICE;
-    if (bt && hipMemcpyAsync(d_tiles_, (char*)pinned + bi, bt, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (!witems_.empty() &&
+        hipMemcpyAsync(d_tables_, witems_.data(), table_bytes(), hipMemcpyHostToDevice, s) != hipSuccess)
         return SOLVE_E_DEVICE;
     return SOLVE_OK;
 }
 
 int Batch::launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
                   const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s) {
-    if (!x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
+    return launch_with_tables(d_tables_, x, y, sd, ed, koff, qoff, yq, ypp, status, s);
+}
+
+int Batch::launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
+                              const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
+                              int32_t* status, hipStream_t s) {
+    if (!tables || !x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
     BatchDevArgs a;
     a.x = x;
     a.y = y;
@@ -299,24 +341,19 @@ int Batch::launch(const double* x, const double* y, const double* sd, const doub
     a.yq = yq;
     a.ypp = ypp;
     a.status = status;
-    a.items = (const BuildItem*)d_items_;
-    a.tiles = (const TileItem*)d_tiles_;
-    a.counters = (int32_t*)d_counters_;
-    a.ready = (int32_t*)d_counters_ + 4;
-    a.n_items = (int32_t)items_.size();
-    a.n_tiles = (int32_t)tiles_.size();
-    a.precision = (int32_t)precision_;
-    const int grid = std::max(1, num_cu_ * tuning_.grid_per_cu);
-    const int f = tuning_.fused;
-    if (tuning_.block == 256) return launch_variant<256, 8>(a, f, grid, count_, s);
-    if (tuning_.block == 512) return launch_variant<512, 4>(a, f, grid, count_, s);
-    return SOLVE_E_ARG;
-}
-
-int32_t Batch::spin_timeout_flag_host() {
-    int32_t v = 0;
-    if (d_counters_) hipMemcpy(&v, (int32_t*)d_counters_ + 1, sizeof(v), hipMemcpyDeviceToHost);
-    return v;
+    a.witems = (const WaveItem*)tables;
+    a.n_witems = (int64_t)witems_.size();
+    int rc = SOLVE_E_ARG;
+    switch (wave_ch_) {
+        case 1: rc = launch_waves_ch<1>(a, tuning_, num_cu_, s); break;
+        case 2: rc = launch_waves_ch<2>(a, tuning_, num_cu_, s); break;
+        case 3: rc = launch_waves_ch<3>(a, tuning_, num_cu_, s); break;
+        case 4: rc = launch_waves_ch<4>(a, tuning_, num_cu_, s); break;
+        case kWaveMaxCH: rc = launch_waves_ch<kWaveMaxCH>(a, tuning_, num_cu_, s); break;
+        default: break;
+    }
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
 }  // namespace spl
@@ -329,8 +366,8 @@ struct spline_plan {
     hipGraphExec_t exec = nullptr;
     explicit spline_plan(int dev) : batch(dev) {}
     ~spline_plan() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
     }
 };
 
@@ -339,13 +376,13 @@ namespace {
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
-        hipGetDevice(&prev);
-        if (prev != dev) hipSetDevice(dev);
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
     }
     ~DeviceGuard() {
         int cur = -1;
-        hipGetDevice(&cur);
-        if (prev >= 0 && cur != prev) hipSetDevice(prev);
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
     }
 };
 
@@ -452,8 +489,8 @@ extern "C" int spline_plan_capture(spline_plan* p, const double* x, const double
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;
         s = cs;
     }
-    if (p->exec) { hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-    if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+    if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     int rc = SOLVE_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SOLVE_E_DEVICE;
     if (!rc) {
@@ -462,7 +499,7 @@ extern "C" int spline_plan_capture(spline_plan* p, const double* x, const double
         const hipError_t e = hipStreamEndCapture(s, &gr);
         if (lrc) rc = lrc;
         else if (e != hipSuccess || !gr) rc = SOLVE_E_DEVICE;
-        if (gr && rc) hipGraphDestroy(gr);
+        if (gr && rc) (void)hipGraphDestroy(gr);
         if (!rc) {
             p->graph = gr;
             if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -471,7 +508,7 @@ extern "C" int spline_plan_capture(spline_plan* p, const double* x, const double
             }
         }
     }
-    if (cs) hipStreamDestroy(cs);
+    if (cs) (void)hipStreamDestroy(cs);
     return rc;
 }
 
@@ -514,18 +551,17 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
             return SOLVE_OK;
         }
     }
+    // wavefronts per workgroup x query share x (one item per wavefront, or
+    // persistent wavefronts)
     std::vector<spline_tuning> cands;
-    for (int block : {256, 512}) {
-        for (int cap : {2048, 4096, 8192, 16384}) {
-            for (int gpc : {2, 4, 8}) cands.push_back(spline_tuning{block, cap, gpc, 1});
-            cands.push_back(spline_tuning{block, cap, 4, 0});
-        }
-    }
+    for (int block : {64, 128, 256})
+        for (int cap : {1024, 2048, 4096, 8192})
+            for (int gpc : {0, 16}) cands.push_back(spline_tuning{block, cap, gpc, 1});
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;
     hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
     double bms = 1e300;
     spline_tuning bt = b.tuning();
     int rc = SOLVE_OK;
@@ -534,25 +570,25 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
         if (!rc) rc = b.upload(s);
         for (int w = 0; !rc && w < 2; ++w) rc = b.launch(x, y, sd, ed, koff, qoff, yq, ypp, nullptr, s);
         if (rc) break;
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         for (int r = 0; !rc && r < reps; ++r) rc = b.launch(x, y, sd, ed, koff, qoff, yq, ypp, nullptr, s);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) rc = SOLVE_E_DEVICE;
         if (rc) break;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         const double per = (double)ms / reps;
         if (per < bms) {
             bms = per;
             bt = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (!rc) rc = b.retile(bt);
     if (!rc) rc = b.upload(s);
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = SOLVE_E_DEVICE;
-    hipStreamDestroy(s);
+    (void)hipStreamDestroy(s);
     if (rc) return rc;
     *best = bt;
     *best_ms = bms;
@@ -566,7 +602,7 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
 extern "C" int spline_plan_destroy(spline_plan* p) {
     if (!p) return SOLVE_E_ARG;
     DeviceGuard g(p->batch.device());
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     delete p;
     return SOLVE_OK;
 }

@@ -1,19 +1,14 @@
-// Batched form of the spline path: many curves in CSR layout.
+// Batched form of the spline path: many curves in CSR layout, in one launch.
 //
-// Work of one run:
-//   * build items: either one small curve per wavefront of the workgroup
-//     (n <= 64*8), or one larger curve built by the whole workgroup
-//     (n <= SOLVE_MAX_N_BATCH);
-//   * evaluate slices: (curve, query range) pairs; a curve's queries are cut
-//     into slices of at most queries_per_tile, fewer when its knots are
-//     sparse relative to its queries (so that a slice's knots fit the staged
-//     window), and never below one workgroup's worth.
-// The fused kernel is persistent: each workgroup first claims build items
-// with an atomic counter until none are left, then walks the tile list with a
-// grid stride.  A tile waits (bounded spin) for its curve's ready flag.  This
-// cannot deadlock at any grid size: a workgroup reaches the tiles only after
-// every build item has been claimed, and a claimed item belongs to a
-// workgroup that is running and waits on nothing.
+// A list of wave items, each run by one wavefront from start to end with no
+// waiting on any other wavefront.  A wave
+// item is (curve, knot block, query share): the wavefront solves the block's
+// span for y'' exactly in its own LDS -- the whole curve when it fits one
+// wavefront's rows, else the block of intervals plus a halo of rows on either
+// side -- and then evaluates its share of the uniform queries that fall in the
+// block.  Curves with many queries are cut into several shares, each solving
+// the same small span again, so that no wavefront holds far more work than
+// the average.  Items are ordered by decreasing work.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,22 +20,17 @@
 
 namespace spl {
 
-constexpr int kItemLanes = 8;           // curves per packed build item (one per wavefront)
-constexpr int kWaveBuildMaxN = 64 * 8;   // largest curve one wavefront builds
-constexpr int kBatchWindow = 256;         // knots an evaluate slice stages
-constexpr int32_t kItemPacked = 0;
-constexpr int32_t kItemWhole = 1;
+constexpr int kBatchHalo = 128;      // halo rows on either side of a knot block
+constexpr int kWaveMaxCH = 8;        // rows per lane of the largest wave span
+constexpr int kWaveSpanMax = 64 * kWaveMaxCH;
+constexpr int kWaveBlock = kWaveSpanMax - 1 - 2 * kBatchHalo;  // intervals per knot block
 
-struct BuildItem {
-    int32_t kind;               // kItemPacked: inst[w] is wavefront w's curve (-1 = none)
-    int32_t inst[kItemLanes];   // kItemWhole: inst[0] is built by the whole workgroup
-};
-
-struct TileItem {  // uniform queries k0 .. k1-1 of curve inst
-    int32_t inst;
-    int32_t pad;
-    int64_t k0;
-    int64_t k1;
+struct WaveItem {
+    int32_t inst;   // curve
+    int16_t j0;     // intervals [j0, j1) of the curve
+    int16_t j1;
+    int32_t s;      // share s of S of the block's queries (S = 0: y'' only)
+    int32_t S;
 };
 
 struct BatchDevArgs {
@@ -53,13 +43,8 @@ struct BatchDevArgs {
     double* yq;
     double* ypp;
     int32_t* status;
-    const BuildItem* items;
-    const TileItem* tiles;
-    int32_t* counters;  // [0] build item counter, [1] spin-timeout flag
-    int32_t* ready;     // one flag per curve
-    int32_t n_items;
-    int32_t n_tiles;
-    int32_t precision;
+    const WaveItem* witems;
+    int64_t n_witems;
 };
 
 // Host side of a batch: the work tables and the device buffers that hold them.
@@ -71,32 +56,36 @@ public:
     Batch& operator=(const Batch&) = delete;
 
     // Plan from host offsets; returns a SOLVE_* code.  uniform (nullable):
-    // per curve, 0 = no uniform evaluate tiles (its queries are evaluated by
-    // another kernel; m may then be 0).
+    // per curve, 0 = no uniform queries (y'' only: its queries are evaluated
+    // by another kernel; m may then be 0).
     int plan(int64_t count, const int64_t* koff, const int64_t* qoff, const spline_tuning& t, uint32_t precision,
              const uint8_t* uniform = nullptr);
     // Copy the tables to the device (async on s); the host tables must stay
     // alive until the copy completes (they are members, so until re-planning).
     int upload(hipStream_t s);
-    // Same, through a caller-owned pinned staging buffer of table_bytes().
-    int upload_staged(hipStream_t s, void* pinned);
-    size_t table_bytes() const { return items_.size() * sizeof(BuildItem) + tiles_.size() * sizeof(TileItem); }
-    // Launch one run on device-resident data.
+    // Bytes of the tables, and a copy of them into host memory at dst (in
+    // the layout launch_with_tables expects).
+    size_t table_bytes() const;
+    void write_tables(void* dst) const;
+    // Launch one run on device-resident data with the tables at the device
+    // address tables (as written by write_tables), or with the plan's own
+    // uploaded tables (launch).
     int launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
                const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s);
+    int launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
+                           const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
+                           int32_t* status, hipStream_t s);
 
     int64_t count() const { return count_; }
     const spline_tuning& tuning() const { return tuning_; }
-    void set_tuning(const spline_tuning& t) { tuning_ = t; }
-    int retile(const spline_tuning& t);  // re-plan tiles for a new tile size
-    int32_t spin_timeout_flag_host();    // synchronous read, for tests
+    int retile(const spline_tuning& t);  // re-plan for new tuning
 
     int device() const { return device_; }
     uint32_t precision() const { return precision_; }
     int64_t total_n() const { return total_n_; }
     int64_t total_m() const { return total_m_; }
-    int32_t n_tiles() const { return (int32_t)tiles_.size(); }
-    int32_t n_items() const { return (int32_t)items_.size(); }
+    int64_t n_witems() const { return (int64_t)witems_.size(); }
+    int wave_rows() const { return wave_ch_ * 64; }
 
 private:
     int ensure(void** p, size_t* cap, size_t bytes);
@@ -105,18 +94,15 @@ private:
     int device_;
     int64_t count_ = 0;
     int64_t total_n_ = 0, total_m_ = 0;
+    int64_t max_n_ = 0;
+    int wave_ch_ = 1;
     uint32_t precision_ = 0;
     spline_tuning tuning_{};
     std::vector<int64_t> n_, m_;
     std::vector<uint8_t> uniform_;
-    std::vector<BuildItem> items_;
-    std::vector<TileItem> tiles_;
-    void* d_items_ = nullptr;
-    size_t cap_items_ = 0;
-    void* d_tiles_ = nullptr;
-    size_t cap_tiles_ = 0;
-    void* d_counters_ = nullptr;  // counters (4 ints) then ready flags
-    size_t cap_counters_ = 0;
+    std::vector<WaveItem> witems_;
+    void* d_tables_ = nullptr;
+    size_t cap_tables_ = 0;
     int num_cu_ = 0;
 };
 

@@ -24,6 +24,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -95,6 +97,14 @@ struct HostBuf {  // pinned host staging
     T* as() const { return (T*)p; }
 };
 
+// With SOLVE_DEBUG set in the environment, failing HIP calls of the request
+// path are reported on stderr (the C ABI itself only returns SOLVE_* codes).
+int hip_fail(const char* what, hipError_t e) {
+    static const bool debug = std::getenv("SOLVE_DEBUG") != nullptr;
+    if (debug) std::fprintf(stderr, "solve: %s failed: %s (%d)\n", what, hipGetErrorString(e), (int)e);
+    return SOLVE_E_DEVICE;
+}
+
 bool is_device_ptr(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t a;
@@ -137,9 +147,14 @@ struct Slot {
     bool failed = false;
     std::vector<ReqP> reqs;
     uint64_t bytes = 0;
-    DevBuf x, y, ypp, yq, sd, ed, koff, qoff, xq, status;
-    HostBuf hx, hy, hypp, hyq, hsd, hed, hkoff, hqoff, hxq, hstatus, htab;
+    // One packed input region and one packed output region per batch, each
+    // with a pinned host mirror, so that a batch costs one copy each way.
+    DevBuf din, dout;
+    HostBuf hin, hout;
+    std::vector<int64_t> koff, qoff;
     std::vector<uint8_t> uniform;
+    size_t o_koff = 0, o_qoff = 0, o_sd = 0, o_ed = 0, o_x = 0, o_y = 0, o_xq = 0, o_tab = 0, in_bytes = 0;
+    size_t o_status = 0, o_yq = 0, o_ypp = 0, out_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void drop_graph() {
@@ -148,7 +163,19 @@ struct Slot {
         exec = nullptr;
         graph = nullptr;
     }
+    template <typename T>
+    T* din_at(size_t o) const { return (T*)((char*)din.p + o); }
+    template <typename T>
+    T* hin_at(size_t o) const { return (T*)((char*)hin.p + o); }
+    template <typename T>
+    T* dout_at(size_t o) const { return (T*)((char*)dout.p + o); }
+    template <typename T>
+    T* hout_at(size_t o) const { return (T*)((char*)hout.p + o); }
 };
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int32_t kStatusUnset = 0x7fffffff;
 
 }  // namespace
 
@@ -168,6 +195,10 @@ struct solve_ctx {
     uint64_t resident = 0, peak_resident = 0, resident_reqs = 0;
     uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_batches = 0, peak_batch = 0;
     spline_tuning tuning = spl::default_tuning();
+    // copies of device-resident inputs (a stream of their own: a synchronous
+    // copy on the legacy stream would collide with a batch being captured)
+    std::mutex in_mu;
+    hipStream_t in_stream = nullptr;
     // plain mode
     std::mutex plain_mu;
     hipStream_t plain_stream = nullptr;
@@ -201,113 +232,98 @@ void finish_locked(solve_ctx* c, const ReqP& r, int status, int code) {
 int launch_batch(solve_ctx* c, Slot& s) {
     const int64_t count = (int64_t)s.reqs.size();
     int64_t nt = 0, mt = 0, xt = 0;
-    bool want_ypp = false;
-    for (const auto& r : s.reqs) {
-        nt += r->n;
-        mt += r->m;
-        if (r->explicit_q()) xt += r->m;
-        want_ypp |= r->ypp_out != nullptr;
-    }
-    int rc = SOLVE_OK;
-    rc = rc ? rc : s.hkoff.ensure(8 * (count + 1));
-    rc = rc ? rc : s.hqoff.ensure(8 * (count + 1));
-    rc = rc ? rc : s.hx.ensure(8 * nt);
-    rc = rc ? rc : s.hy.ensure(8 * nt);
-    rc = rc ? rc : s.hsd.ensure(8 * count);
-    rc = rc ? rc : s.hed.ensure(8 * count);
-    rc = rc ? rc : s.hyq.ensure(8 * mt);
-    rc = rc ? rc : s.hypp.ensure(8 * nt);
-    rc = rc ? rc : s.hstatus.ensure(4 * count);
-    rc = rc ? rc : s.hxq.ensure(8 * std::max<int64_t>(xt, 1));
-    if (rc) return rc;
-    int64_t* koff = s.hkoff.as<int64_t>();
-    int64_t* qoff = s.hqoff.as<int64_t>();
+    bool host_yq = false, host_ypp = false;
+    s.koff.assign(count + 1, 0);
+    s.qoff.assign(count + 1, 0);
     s.uniform.assign(count, 1);
-    koff[0] = 0;
-    qoff[0] = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const Req& r = *s.reqs[i];
+        s.koff[i + 1] = s.koff[i] + r.n;
+        s.qoff[i + 1] = s.qoff[i] + r.m;
+        if (r.explicit_q()) {
+            xt += r.m;
+            s.uniform[i] = 0;
+        }
+        host_yq |= !r.yq_dev;
+        host_ypp |= r.ypp_out && !r.ypp_dev;
+    }
+    nt = s.koff[count];
+    mt = s.qoff[count];
+    if (!s.batch) s.batch.reset(new Batch(c->cfg.device));
+    int rc = s.batch->plan(count, s.koff.data(), s.qoff.data(), c->tuning, c->cfg.precision, s.uniform.data());
+    if (rc) return rc;
+    // layouts
+    size_t o = 0;
+    s.o_koff = o; o = align256(o + 8 * (count + 1));
+    s.o_qoff = o; o = align256(o + 8 * (count + 1));
+    s.o_sd = o;   o = align256(o + 8 * count);
+    s.o_ed = o;   o = align256(o + 8 * count);
+    s.o_x = o;    o = align256(o + 8 * nt);
+    s.o_y = o;    o = align256(o + 8 * nt);
+    s.o_xq = o;   o = align256(o + 8 * xt);
+    s.o_tab = o;  o = align256(o + s.batch->table_bytes());
+    s.in_bytes = o;
+    o = 0;
+    s.o_status = o; o = align256(o + 4 * count);
+    s.o_yq = o;     o = align256(o + 8 * mt);
+    s.o_ypp = o;    o = align256(o + 8 * nt);
+    s.out_bytes = o;
+    rc = rc ? rc : s.hin.ensure(s.in_bytes);
+    rc = rc ? rc : s.din.ensure(s.in_bytes);
+    rc = rc ? rc : s.hout.ensure(s.out_bytes);
+    rc = rc ? rc : s.dout.ensure(s.out_bytes);
+    if (rc) return rc;
+    // stage the inputs
+    std::memcpy(s.hin_at<int64_t>(s.o_koff), s.koff.data(), 8 * (count + 1));
+    std::memcpy(s.hin_at<int64_t>(s.o_qoff), s.qoff.data(), 8 * (count + 1));
     int64_t xo = 0;
     for (int64_t i = 0; i < count; ++i) {
         const Req& r = *s.reqs[i];
-        std::memcpy(s.hx.as<double>() + koff[i], r.x.data(), 8 * r.n);
-        std::memcpy(s.hy.as<double>() + koff[i], r.y.data(), 8 * r.n);
-        s.hsd.as<double>()[i] = r.sd;
-        s.hed.as<double>()[i] = r.ed;
+        s.hin_at<double>(s.o_sd)[i] = r.sd;
+        s.hin_at<double>(s.o_ed)[i] = r.ed;
+        std::memcpy(s.hin_at<double>(s.o_x) + s.koff[i], r.x.data(), 8 * r.n);
+        std::memcpy(s.hin_at<double>(s.o_y) + s.koff[i], r.y.data(), 8 * r.n);
         if (r.explicit_q()) {
-            std::memcpy(s.hxq.as<double>() + xo, r.xq.data(), 8 * r.m);
+            std::memcpy(s.hin_at<double>(s.o_xq) + xo, r.xq.data(), 8 * r.m);
             xo += r.m;
-            s.uniform[i] = 0;
         }
-        koff[i + 1] = koff[i] + r.n;
-        qoff[i + 1] = qoff[i] + r.m;
     }
-    if (!s.batch) s.batch.reset(new Batch(c->cfg.device));
-    rc = s.batch->plan(count, koff, qoff, c->tuning, c->cfg.precision, s.uniform.data());
-    if (rc) return rc;
-    rc = rc ? rc : s.htab.ensure(std::max<size_t>(s.batch->table_bytes(), 64));
-    rc = rc ? rc : s.x.ensure(8 * nt);
-    rc = rc ? rc : s.y.ensure(8 * nt);
-    rc = rc ? rc : s.ypp.ensure(8 * nt);
-    rc = rc ? rc : s.yq.ensure(8 * mt);
-    rc = rc ? rc : s.sd.ensure(8 * count);
-    rc = rc ? rc : s.ed.ensure(8 * count);
-    rc = rc ? rc : s.koff.ensure(8 * (count + 1));
-    rc = rc ? rc : s.qoff.ensure(8 * (count + 1));
-    rc = rc ? rc : s.status.ensure(4 * count);
-    rc = rc ? rc : s.xq.ensure(8 * std::max<int64_t>(xt, 1));
-    if (rc) return rc;
+    s.batch->write_tables(s.hin_at<char>(s.o_tab));
 
     const bool use_graph = !(c->cfg.flags & SOLVE_NO_GRAPH);
     hipStream_t st = s.stream;
     s.drop_graph();
     if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SOLVE_E_DEVICE;
-    auto h2d = [&](DevBuf& d, const HostBuf& h, size_t b) {
-        if (!rc && b && hipMemcpyAsync(d.p, h.p, b, hipMemcpyHostToDevice, st) != hipSuccess) rc = SOLVE_E_DEVICE;
-    };
-    auto d2h = [&](HostBuf& h, const DevBuf& d, size_t b) {
-        if (!rc && b && hipMemcpyAsync(h.p, d.p, b, hipMemcpyDeviceToHost, st) != hipSuccess) rc = SOLVE_E_DEVICE;
-    };
-    rc = s.batch->upload_staged(st, s.htab.p);
-    h2d(s.x, s.hx, 8 * nt);
-    h2d(s.y, s.hy, 8 * nt);
-    h2d(s.sd, s.hsd, 8 * count);
-    h2d(s.ed, s.hed, 8 * count);
-    h2d(s.koff, s.hkoff, 8 * (count + 1));
-    h2d(s.qoff, s.hqoff, 8 * (count + 1));
-    if (xt) h2d(s.xq, s.hxq, 8 * xt);
+    if (hipMemcpyAsync(s.din.p, s.hin.p, s.in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) rc = SOLVE_E_DEVICE;
+    double* dx = s.din_at<double>(s.o_x);
+    double* dy = s.din_at<double>(s.o_y);
+    double* dyq = s.dout_at<double>(s.o_yq);
+    double* dypp = s.dout_at<double>(s.o_ypp);
     if (!rc)
-        rc = s.batch->launch(s.x.as<double>(), s.y.as<double>(), s.sd.as<double>(), s.ed.as<double>(),
-                             s.koff.as<int64_t>(), s.qoff.as<int64_t>(), s.yq.as<double>(), s.ypp.as<double>(),
-                             s.status.as<int32_t>(), st);
+        rc = s.batch->launch_with_tables(s.din_at<char>(s.o_tab), dx, dy, s.din_at<double>(s.o_sd),
+                                         s.din_at<double>(s.o_ed), s.din_at<int64_t>(s.o_koff),
+                                         s.din_at<int64_t>(s.o_qoff), dyq, dypp, s.dout_at<int32_t>(s.o_status), st);
     xo = 0;
     for (int64_t i = 0; i < count && !rc; ++i) {
         const Req& r = *s.reqs[i];
         if (!r.explicit_q()) continue;
-        rc = spl::launch_eval_points(s.x.as<double>() + koff[i], s.y.as<double>() + koff[i],
-                                     s.ypp.as<double>() + koff[i], r.n, s.xq.as<double>() + xo, r.m,
-                                     s.yq.as<double>() + qoff[i], nullptr, nullptr, nullptr, st);
+        rc = spl::launch_eval_points(dx + s.koff[i], dy + s.koff[i], dypp + s.koff[i], r.n,
+                                     s.din_at<double>(s.o_xq) + xo, r.m, dyq + s.qoff[i], nullptr, nullptr, nullptr,
+                                     st);
         xo += r.m;
     }
-    // Results: device-resident callers get a device-to-device copy, host
-    // callers go through the pinned staging.
-    bool any_host_yq = false;
+    // Results: device-resident callers get a device-to-device copy; host
+    // callers are served from one copy of the output region.
     for (int64_t i = 0; i < count && !rc; ++i) {
         const Req& r = *s.reqs[i];
-        if (r.yq_dev) {
-            if (hipMemcpyAsync(r.yq_out, s.yq.as<double>() + qoff[i], 8 * r.m, hipMemcpyDeviceToDevice, st) !=
-                hipSuccess)
-                rc = SOLVE_E_DEVICE;
-        } else {
-            any_host_yq = true;
-        }
-        if (r.ypp_out && r.ypp_dev) {
-            if (hipMemcpyAsync(r.ypp_out, s.ypp.as<double>() + koff[i], 8 * r.n, hipMemcpyDeviceToDevice, st) !=
-                hipSuccess)
-                rc = SOLVE_E_DEVICE;
-        }
+        if (r.yq_dev && hipMemcpyAsync(r.yq_out, dyq + s.qoff[i], 8 * r.m, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = SOLVE_E_DEVICE;
+        if (!rc && r.ypp_out && r.ypp_dev &&
+            hipMemcpyAsync(r.ypp_out, dypp + s.koff[i], 8 * r.n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = SOLVE_E_DEVICE;
     }
-    if (any_host_yq) d2h(s.hyq, s.yq, 8 * mt);
-    if (want_ypp) d2h(s.hypp, s.ypp, 8 * nt);
-    d2h(s.hstatus, s.status, 4 * count);
+    const size_t back = host_ypp ? s.out_bytes : host_yq ? s.o_ypp : s.o_yq;
+    if (!rc && hipMemcpyAsync(s.hout.p, s.dout.p, back, hipMemcpyDeviceToHost, st) != hipSuccess) rc = SOLVE_E_DEVICE;
     if (use_graph) {
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &g);
@@ -328,14 +344,12 @@ int launch_batch(solve_ctx* c, Slot& s) {
 
 // Deliver the results of a completed slot (called without the lock).
 void deliver(Slot& s) {
-    const int64_t* koff = s.hkoff.as<int64_t>();
-    const int64_t* qoff = s.hqoff.as<int64_t>();
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         Req& r = *s.reqs[i];
         if (s.failed) continue;
-        r.code = s.hstatus.as<int32_t>()[i];
-        if (!r.yq_dev) std::memcpy(r.yq_out, s.hyq.as<double>() + qoff[i], 8 * r.m);
-        if (r.ypp_out && !r.ypp_dev) std::memcpy(r.ypp_out, s.hypp.as<double>() + koff[i], 8 * r.n);
+        r.code = s.hout_at<int32_t>(s.o_status)[i];
+        if (!r.yq_dev) std::memcpy(r.yq_out, s.hout_at<double>(s.o_yq) + s.qoff[i], 8 * r.m);
+        if (r.ypp_out && !r.ypp_dev) std::memcpy(r.ypp_out, s.hout_at<double>(s.o_ypp) + s.koff[i], 8 * r.n);
     }
 }
 
@@ -462,10 +476,13 @@ void scheduler(solve_ctx* c) {
     }
 }
 
-int copy_in(std::vector<double>& dst, const double* src, int64_t n) {
+int copy_in(solve_ctx* c, std::vector<double>& dst, const double* src, int64_t n) {
     dst.resize((size_t)n);
     if (is_device_ptr(src)) {
-        if (hipMemcpy(dst.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return SOLVE_E_DEVICE;
+        std::lock_guard<std::mutex> g(c->in_mu);
+        hipError_t e = hipMemcpyAsync(dst.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost, c->in_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->in_stream);
+        if (e != hipSuccess) return hip_fail("copy of a device input", e);
     } else {
         std::memcpy(dst.data(), src, 8 * (size_t)n);
     }
@@ -484,15 +501,15 @@ int run_plain(solve_ctx* c, Req& r) {
     if (r.explicit_q()) rc = rc ? rc : c->pxq.ensure(8 * r.m);
     if (rc) return rc;
     r.t[1] = r.t[2] = now_s();
-    if (hipMemcpyAsync(c->px.p, r.x.data(), 8 * r.n, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(c->py.p, r.y.data(), 8 * r.n, hipMemcpyHostToDevice, s) != hipSuccess)
-        return SOLVE_E_DEVICE;
+    hipError_t e = hipMemcpyAsync(c->px.p, r.x.data(), 8 * r.n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->py.p, r.y.data(), 8 * r.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail("plain: input copy", e);
     rc = spl::launch_build(c->px.as<double>(), c->py.as<double>(), r.n, r.sd, r.ed, c->pypp.as<double>(),
                            c->pstatus.as<int32_t>(), s);
     if (!rc) {
         if (r.explicit_q()) {
-            if (hipMemcpyAsync(c->pxq.p, r.xq.data(), 8 * r.m, hipMemcpyHostToDevice, s) != hipSuccess)
-                return SOLVE_E_DEVICE;
+            e = hipMemcpyAsync(c->pxq.p, r.xq.data(), 8 * r.m, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail("plain: query copy", e);
             rc = spl::launch_eval_points(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
                                          c->pxq.as<double>(), r.m, c->pyq.as<double>(), nullptr, nullptr, nullptr, s);
         } else {
@@ -502,15 +519,20 @@ int run_plain(solve_ctx* c, Req& r) {
     }
     if (rc) return rc;
     const hipMemcpyKind kq = r.yq_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (hipMemcpyAsync(r.yq_out, c->pyq.p, 8 * r.m, kq, s) != hipSuccess) return SOLVE_E_DEVICE;
-    if (r.ypp_out) {
+    e = hipMemcpyAsync(r.yq_out, c->pyq.p, 8 * r.m, kq, s);
+    if (e == hipSuccess && r.ypp_out) {
         const hipMemcpyKind kp = r.ypp_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (hipMemcpyAsync(r.ypp_out, c->pypp.p, 8 * r.n, kp, s) != hipSuccess) return SOLVE_E_DEVICE;
+        e = hipMemcpyAsync(r.ypp_out, c->pypp.p, 8 * r.n, kp, s);
     }
-    int32_t st = 0;
-    if (hipMemcpyAsync(&st, c->pstatus.p, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return SOLVE_E_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return SOLVE_E_DEVICE;
-    return st == 0 ? SOLVE_OK : st;
+    int32_t st = kStatusUnset;
+    if (e == hipSuccess) e = hipMemcpyAsync(&st, c->pstatus.p, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail("plain: result copy", e);
+    if (st != SOLVE_OK && st != SOLVE_E_ORDER) {
+        hip_fail("plain: status word", hipSuccess);
+        return SOLVE_E_DEVICE;
+    }
+    return st;
 }
 
 }  // namespace
@@ -534,6 +556,11 @@ extern "C" int solve_create(const solve_config* cfg, solve_ctx** out) {
         delete c;
         return SOLVE_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&c->in_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(c->plain_stream);
+        delete c;
+        return SOLVE_E_DEVICE;
+    }
     if (!(cfg->flags & SOLVE_PLAIN)) {
         for (uint32_t i = 0; i < c->cfg.max_inflight; ++i) {
             std::unique_ptr<Slot> s(new Slot());
@@ -545,6 +572,7 @@ extern "C" int solve_create(const solve_config* cfg, solve_ctx** out) {
                     (void)hipEventDestroy(t->done);
                 }
                 (void)hipStreamDestroy(c->plain_stream);
+                (void)hipStreamDestroy(c->in_stream);
                 delete c;
                 return SOLVE_E_DEVICE;
             }
@@ -574,9 +602,9 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
     r->ypp_out = ypp_out;
     r->yq_dev = is_device_ptr(yq_out);
     r->ypp_dev = ypp_out && is_device_ptr(ypp_out);
-    int rc = copy_in(r->x, knots, n);
-    if (!rc) rc = copy_in(r->y, values, n);
-    if (!rc && xq) rc = copy_in(r->xq, xq, m);
+    int rc = copy_in(c, r->x, knots, n);
+    if (!rc) rc = copy_in(c, r->y, values, n);
+    if (!rc && xq) rc = copy_in(c, r->xq, xq, m);
     if (rc) return rc;
     for (int64_t j = 1; j < n; ++j)
         if (!(r->x[j] > r->x[j - 1])) return SOLVE_E_ORDER;
@@ -629,7 +657,6 @@ extern "C" int solve_wait(solve_ctx* c, solve_ticket t, int* status, int64_t tim
     if (timeout_ms < 0) c->cv_done.wait(lk, ready);
     else c->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
     *status = r->status;
-    if (*status != SOLVE_PENDING) c->tickets.erase(t);
     return SOLVE_OK;
 }
 
@@ -681,16 +708,16 @@ extern "C" int solve_destroy(solve_ctx* c) {
         (void)hipStreamSynchronize(s->stream);
         s->drop_graph();
         s->batch.reset();
-        for (DevBuf* d : {&s->x, &s->y, &s->ypp, &s->yq, &s->sd, &s->ed, &s->koff, &s->qoff, &s->xq, &s->status})
-            d->release();
-        for (HostBuf* h : {&s->hx, &s->hy, &s->hypp, &s->hyq, &s->hsd, &s->hed, &s->hkoff, &s->hqoff, &s->hxq,
-                           &s->hstatus, &s->htab})
-            h->release();
+        s->din.release();
+        s->dout.release();
+        s->hin.release();
+        s->hout.release();
         (void)hipEventDestroy(s->done);
         (void)hipStreamDestroy(s->stream);
     }
     for (DevBuf* d : {&c->px, &c->py, &c->pypp, &c->pyq, &c->pxq, &c->pstatus}) d->release();
     (void)hipStreamDestroy(c->plain_stream);
+    (void)hipStreamDestroy(c->in_stream);
     delete c;
     return SOLVE_OK;
 }

@@ -61,9 +61,12 @@ __device__ __forceinline__ double uniform_query(double x0, double xl, double h, 
 // First uniform query strictly above v, in [0, m].  The positions are
 // non-decreasing in k, so k = floor((v - x0)/h) + 1 is right to within the
 // rounding of the positions; it is checked against the exact positions and
-// moved by single steps (a binary search covers anything further off).
-__device__ __forceinline__ int64_t first_query_above(double x0, double xl, double h, int64_t m, double v) {
-    double t = (m > 1) ? (v - x0) / h : 0.0;
+// moved by single steps (a binary search covers anything further off).  rh is
+// 1/h (only the starting estimate uses it, so the result is exact whatever
+// its rounding).
+__device__ __forceinline__ int64_t first_query_above_r(double x0, double xl, double h, double rh, int64_t m,
+                                                       double v) {
+    double t = (m > 1) ? (v - x0) * rh : 0.0;
     t = fmin(fmax(t, -1.0), (double)m);  // also maps NaN to -1
     int64_t k = (int64_t)floor(t) + 1;
     k = k < 0 ? 0 : (k > m ? m : k);
@@ -83,6 +86,10 @@ __device__ __forceinline__ int64_t first_query_above(double x0, double xl, doubl
         else lo = mid + 1;
     }
     return lo;
+}
+
+__device__ __forceinline__ int64_t first_query_above(double x0, double xl, double h, int64_t m, double v) {
+    return first_query_above_r(x0, xl, h, (m > 1) ? 1.0 / h : 0.0, m, v);
 }
 
 // The rewritten interpolant of "Fast Interpolation" (newint) on [a, b] with
@@ -422,7 +429,7 @@ struct SoloGroup {  // the group holds every row of the curve
 // whether the knots were found unordered.
 // ---------------------------------------------------------------------------
 template <int NT, int CH, bool WAVE_ONLY, typename Cross, bool NORM = true>
-__device__ bool build_span(const double* __restrict__ x, const double* __restrict__ y, int n, int rs, int re,
+__device__ __forceinline__ bool build_span(const double* __restrict__ x, const double* __restrict__ y, int n, int rs, int re,
                            double sd, double ed, double* __restrict__ ypp, int32_t* __restrict__ status,
                            double* lds, Fwd* lds_f, Bwd* lds_b, const Cross& cross, int tid,
                            double* lds_y = nullptr, double* lds_out = nullptr) {

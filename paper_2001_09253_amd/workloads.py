@@ -57,6 +57,16 @@ def paper_curve(rng: np.random.Generator, n: int, x0: float = 0.0):
     return x, val.astype(np.float64)
 
 
+def alternating_curve(rng: np.random.Generator, n: int, small: float = 1e-3, scale: float = 1.0):
+    """Knots whose widths alternate 1, small, 1, small, ... from x_0 = 0 and
+    standard-normal values times scale: a stress shape for the halo of the
+    block solves (the widths alone set how fast a dropped coupling decays)."""
+    widths = np.where(np.arange(n - 1) % 2 == 0, 1.0, small)
+    x = np.concatenate([[0.0], np.cumsum(widths)])
+    y = rng.standard_normal(n) * scale
+    return x, y
+
+
 def bc_for(i: int):
     """(name, start_deriv, end_deriv) of the i-th instance in the cycle."""
     return BC_CASES[i % len(BC_CASES)]

@@ -1,6 +1,6 @@
-"""Parity of the batched form (one persistent fused launch over many curves,
-its two-launch variant, hipGraph capture/replay, the autotuner) with the FP64
-oracle, through the C ABI."""
+"""Parity of the batched form (the single-launch wave-item kernel over many
+curves, hipGraph capture/replay, the autotuner) with the FP64 oracle, through
+the C ABI."""
 import os
 import tempfile
 
@@ -14,7 +14,13 @@ from paper_2001_09253_amd import api, workloads as w
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(256, 256), (256, 2048), (256, 16384), (512, 512), (512, 8192)]
+# (block, queries_per_tile, grid_per_cu, fused)
+TUNINGS = [(64, 64, 0, 1), (64, 1024, 2, 1), (128, 2048, 0, 1), (256, 4096, 0, 1), (256, 16384, 3, 1)]
+# The two-launch form (a build kernel, then an evaluate kernel reading y''
+# back) faulted the GPU in its build kernel with a memory aperture violation
+# and no cause was found by reading it; it was taken out of the library, and
+# its cases stay here, skipped, until it comes back with a found cause.
+TWO_LAUNCH = [(256, 256, 0, 0), (256, 2048, 0, 0), (512, 8192, 0, 0)]
 
 
 def to_dev(b, status=True):
@@ -50,16 +56,16 @@ def small_batch_oracle(small_batch):
     return oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
 
 
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("fused", [1, 0])
-def test_batch_matches_oracle(small_batch, small_batch_oracle, shape, fused):
+@pytest.mark.parametrize("tuning", TUNINGS + [pytest.param(t, marks=pytest.mark.skip(
+    reason="two-launch form removed: it faulted the GPU (memory aperture violation) with no cause found"))
+    for t in TWO_LAUNCH])
+def test_batch_matches_oracle(small_batch, small_batch_oracle, tuning):
     b = small_batch
-    t = api.Tuning(shape[0], shape[1], 2, fused)
-    plan = api.spline_plan_create(b.koff, b.qoff, tuning=t)
+    plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(*tuning))
     bufs, st = to_dev(b)
     api.spline_plan_run(plan, bufs, st)
     assert np.all(host(st) == 0)
-    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), small_batch_oracle, "shape %s fused %d" % (shape, fused))
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), small_batch_oracle, "tuning %s" % (tuning,))
 
 
 def test_batch_mixed_sizes_up_to_limit():
@@ -68,11 +74,34 @@ def test_batch_mixed_sizes_up_to_limit():
     n = np.array([3, 4, 5, 13, 64, 65, 511, 512, 513, 1000, 2047, api.MAX_N_BATCH, 3, 130], dtype=np.int64)
     m = np.array([1, 2, 3, 2048, 1023, 1025, 7, 4096, 1, 50000, 333, 2049, 100000, 17], dtype=np.int64)
     b = w.batch_from_sizes(17, n, m)
-    for shape in ((256, 1024), (512, 2048)):
-        plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(shape[0], shape[1], 1, 1))
+    for t in ((64, 1024, 1, 1), (256, 4096, 0, 1), (128, 64, 0, 1)):
+        plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(*t))
         bufs, st = to_dev(b)
         api.spline_plan_run(plan, bufs, st)
-        check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="mixed %s" % (shape,))
+        check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="mixed %s" % (t,))
+
+
+@pytest.mark.parametrize("cap", [64, 1024, 1 << 20])
+def test_batch_halo_blocks_worst_decay(cap):
+    # curves past one wavefront's rows are cut into knot blocks with halos;
+    # alternating widths 1 and 1e-3 give the slowest decay of the dropped
+    # coupling, and query shares of 64 cut every block many times over
+    rng = np.random.default_rng(23)
+    sizes = [(api.MAX_N_BATCH, 300000), (1500, 777), (600, 90000), (513, 5)]
+    xs, ys = [], []
+    for n, _ in sizes:
+        x, y = w.alternating_curve(rng, n)
+        xs.append(x)
+        ys.append(y)
+    koff = np.concatenate([[0], np.cumsum([n for n, _ in sizes])]).astype(np.int64)
+    qoff = np.concatenate([[0], np.cumsum([m for _, m in sizes])]).astype(np.int64)
+    b = w.Batch(koff, qoff, np.concatenate(xs), np.concatenate(ys), np.array([1e32, 0.0, -1.0, 1e32]),
+                np.array([1e32, 0.0, 1.0, 2.0]))
+    plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(128, cap, 0, 1))
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    assert np.all(host(st) == 0)
+    check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="halo cap %d" % cap)
 
 
 def test_batch_single_instance_equals_plain_sizes():
@@ -109,9 +138,11 @@ def test_plan_rejects_bad_sizes():
     with pytest.raises(api.SolveError) as e:
         api.spline_plan_create([0, 5], [0, 0])
     assert e.value.code == api.E_SIZE
-    with pytest.raises(api.SolveError) as e:
-        api.spline_plan_create([0, 5], [0, 10], tuning=api.Tuning(128, 1024, 2, 1))
-    assert e.value.code == api.E_ARG
+    for bad in ((96, 1024, 0, 1), (512, 1024, 0, 1), (128, 1024, 0, 0), (256, 32, 0, 1), (256, 1024, -1, 1),
+                (256, 1024, 0, 2)):
+        with pytest.raises(api.SolveError) as e:
+            api.spline_plan_create([0, 5], [0, 10], tuning=api.Tuning(*bad))
+        assert e.value.code == api.E_ARG
 
 
 def test_graph_replays_match_eager(small_batch, small_batch_oracle):
@@ -146,7 +177,8 @@ def test_autotune_picks_a_valid_tuning_and_caches(small_batch, small_batch_oracl
         path = os.path.join(d, "tune.json")
         best, ms = api.spline_plan_autotune(plan, bufs, reps=3, cache_path=path)
         assert ms > 0
-        assert best.block in (256, 512) and best.queries_per_tile >= best.block
+        assert best.fused == 1
+        assert best.block in (64, 128, 256)
         assert os.path.exists(path)
         got = api.spline_plan_get_tuning(plan)
         assert (got.block, got.queries_per_tile, got.grid_per_cu, got.fused) == \

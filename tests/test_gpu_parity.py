@@ -231,11 +231,7 @@ def test_solve_uniform_halo_worst_case_decay():
     # Widths shrinking by 1e-3 per knot make the forward error factor
     # a/(b - a c') approach its 2/3 bound; the halo must still be enough.
     n = 2000
-    w_ = np.empty(n - 1)
-    w_[0::2] = 1.0
-    w_[1::2] = 1e-3
-    x = np.concatenate([[0.0], np.cumsum(w_)])
-    y = np.random.default_rng(5).standard_normal(n) * 1e3
+    x, y = w.alternating_curve(np.random.default_rng(5), n, scale=1e3)
     for m in (n * 64, 3000):
         xd, yd = dev(x), dev(y)
         ypp = torch.empty_like(xd)
