@@ -214,7 +214,8 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
  * whole curve when n <= 512 (n <= 256 when every curve of the batch is that
  * small), else 255 intervals plus 128 halo rows on either side, whose dropped
  * coupling is below 4.5 (2/3)^128 of max|y''| -- and evaluates its queries;
- * wavefronts never wait on one another.
+ * wavefronts never wait on one another.  With tuning.fused = 2 the curves of
+ * up to 256 knots are solved by a first launch instead.
  * ========================================================================== */
 
 typedef struct spline_plan spline_plan;
@@ -224,7 +225,9 @@ typedef struct spline_plan spline_plan;
  * queries per work item (64 .. 2^24); grid_per_cu = 0 for one work item per
  * wavefront (the hardware dispatcher balances), else at most that many
  * persistent workgroups per compute unit (1..64) striding over the items;
- * fused must be 1 (the single-launch kernel is the only form). */
+ * fused = 1: one launch, every work item solves its own span; fused = 2: two
+ * launches, curves of up to 256 knots solved first (16 lanes per curve, four
+ * curves per wavefront) and their work items only evaluate. */
 typedef struct {
     int32_t block;
     int32_t queries_per_tile;

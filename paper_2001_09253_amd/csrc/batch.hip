@@ -18,75 +18,138 @@
 
 namespace spl {
 
-struct alignas(16) IntervalConst {  // 1/(b - a) and (b - a)^2 of one interval
-    double inv, ba2;
-};
+// ---------------------------------------------------------------------------
+// Phase 1: the curves of at most kLaneBuildMaxN knots, kGroupLanes lanes each
+// (one DPP row, so four curves per wavefront): the rows of a1-a4 split into
+// consecutive chunks, one per lane, the paper's forward elimination and back
+// substitution run over each chunk, and the chunks joined by 4-step scans
+// inside the row.  The list is sorted by n, so the curves sharing a wavefront
+// have similar lengths.
+// ---------------------------------------------------------------------------
+constexpr int kGroupLanes = 16;
+constexpr int kGroupsPerBlock = 16;  // 256 threads
+
+template <int CH>
+__global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void group_build_kernel(BatchDevArgs a) {
+    __shared__ double lds[kGroupsPerBlock][kGroupLanes * CH + 2];
+    const int grp = threadIdx.x / kGroupLanes;
+    const int gl = threadIdx.x & (kGroupLanes - 1);
+    const int64_t slot = (int64_t)blockIdx.x * kGroupsPerBlock + grp;
+    const bool has = slot < a.n_lane;  // groups past the list run with no rows
+    const int i = has ? a.lane_curves[slot] : 0;
+    const int64_t ko = has ? a.koff[i] : 0;
+    const int n = has ? (int)(a.koff[i + 1] - ko) : 0;
+    // spans of at most 256 rows: the per-row scaling alone keeps the scan's
+    // entries inside the double range, so the scan does not normalise
+    build_span<kGroupLanes, CH, true, SoloGroup, false>(
+        a.x + ko, a.y + ko, n, 0, n, has ? a.sd[i] : 0.0, has ? a.ed[i] : 0.0, has ? a.ypp + ko : nullptr,
+        (has && a.status) ? a.status + i : nullptr, lds[grp], nullptr, nullptr, SoloGroup{}, gl);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: wave items.
+// ---------------------------------------------------------------------------
 
 // One wavefront's LDS: the span's knots, values and second derivatives (knot j
-// at [j - max(rs - 1, 0)], y'' of row j at so[j - rs]) and the constants of the
-// owned intervals (interval t at ib[t - j0]).
+// at [j - max(rs - 1, 0)], y'' of row j at so[j - rs]), 1/(b - a) of the owned
+// intervals (interval t at inv[t - j0]) and, on the interval-major path, the
+// first query of each touched interval relative to the share's first query.
 template <int CH>
 struct WaveSmem {
     static constexpr int kRows = kWave * CH;
     double sx[kRows + 2];
     double sy[kRows + 2];
     double so[kRows + 2];
-    IntervalConst ib[kRows];
+    double inv[kRows];
+    int32_t bq[kRows + 1];
 };
 
-// Whether x[0..n) fails to increase strictly (or holds a NaN); every lane of
-// the wavefront gets the answer.
-__device__ __forceinline__ bool wave_unordered(const double* __restrict__ x, int n, int lane) {
-    bool bad = false;
-    for (int j = 1 + lane; j < n; j += kWave) bad |= !(x[j] > x[j - 1]);
-    return __ballot(bad) != 0ull;
-}
-
-// One wave item.  All 64 lanes of the wavefront call this.
-template <int CH>
+// One wave item.  All 64 lanes of the wavefront call this.  BUILD: items of
+// curves past a.prebuilt_max_n knots solve their span here; curves up to that
+// length were built by phase 1.
+template <int CH, bool BUILD>
 __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem<CH>& sm, int lane) {
     const int i = it.inst;
-    const int64_t ko = a.koff[i];
-    const int n = (int)(a.koff[i + 1] - ko);
-    const int64_t qo = a.qoff[i];
-    const int64_t m = a.qoff[i + 1] - qo;
+    const int64_t ko = it.ko;
+    const int n = it.n;
+    const int64_t qo = it.qo;
+    const int64_t m = it.m;
     const double* __restrict__ x = a.x + ko;
     const double* __restrict__ y = a.y + ko;
     const int j0 = it.j0;
     const int j1 = it.j1;
-    const bool whole = j0 == 0 && j1 == n - 1;
-    const bool reporter = j0 == 0 && it.s == 0;  // writes the curve's status (and NaNs if it is bad)
-    // a1-a4: y'' over the span, exact for a whole curve and exact to rounding
-    // with the halo (the dropped coupling decays by 2/3 or better per row).
-    const int rs = whole ? 0 : max(0, j0 - kBatchHalo);
-    const int re = whole ? n : min(n, j1 + 1 + kBatchHalo);
-    bool bad = build_span<kWave, CH, true, SoloGroup, true>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr, nullptr,
-                                                             sm.sx, nullptr, nullptr, SoloGroup{}, lane, sm.sy,
-                                                             sm.so);
-    if (!whole) bad = bad || wave_unordered(x, n, lane);
-    if (bad) {
-        if (reporter) {
-            const double nan = __builtin_nan("");
-            if (a.ypp)
-                for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = nan;
-            if (it.S > 0)
-                for (int64_t k = lane; k < m; k += kWave) a.yq[qo + k] = nan;
-            if (a.status && lane == 0) a.status[i] = kStatusOrder;
+    const bool reporter = j0 == 0 && it.s == 0;  // fills the outputs of a bad curve with NaN
+    int rs = 0, re = n;
+    if (!BUILD || n <= a.prebuilt_max_n) {
+        // y'' from phase 1: stage the whole curve (n <= 64 CH), every load
+        // issued before the first store to LDS
+        double rx[CH], ry[CH], rp[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int j = lane + c * kWave;
+            if (j < n) {
+                rx[c] = x[j];
+                ry[c] = y[j];
+                rp[c] = a.ypp[ko + j];
+            }
         }
-        return;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int j = lane + c * kWave;
+            if (j < n) {
+                sm.sx[j] = rx[c];
+                sm.sy[j] = ry[c];
+                sm.so[j] = rp[c];
+            }
+        }
+        wave_sync();
+        bool b = false;
+        for (int j = 1 + lane; j < n; j += kWave) b |= !(sm.sx[j] > sm.sx[j - 1]);
+        if (__ballot(b) != 0ull) {
+            if (reporter && it.S > 0) {
+                const double nan = __builtin_nan("");
+                for (int64_t k = lane; k < m; k += kWave) a.yq[qo + k] = nan;
+            }
+            return;
+        }
+        if (it.S == 0) return;
+    } else {
+        // a1-a4 over the block's span, exact to rounding with the halo (the
+        // dropped coupling decays by 2/3 or better per row); the whole curve
+        // when it fits one wavefront's rows
+        const bool whole = j0 == 0 && j1 == n - 1;
+        rs = whole ? 0 : max(0, j0 - kBatchHalo);
+        re = whole ? n : min(n, j1 + 1 + kBatchHalo);
+        // (at most 512 rows: the per-row scaling keeps the scan's entries
+        // inside the double range without normalising)
+        bool bad = build_span<kWave, CH, true, SoloGroup, false>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr,
+                                                                  nullptr, sm.sx, nullptr, nullptr, SoloGroup{}, lane,
+                                                                  sm.sy, sm.so);
+        if (!whole) {
+            bool b = false;
+            for (int j = 1 + lane; j < n; j += kWave) b |= !(x[j] > x[j - 1]);
+            bad = bad || (__ballot(b) != 0ull);
+        }
+        if (bad) {
+            if (reporter) {
+                const double nan = __builtin_nan("");
+                if (a.ypp)
+                    for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = nan;
+                if (it.S > 0)
+                    for (int64_t k = lane; k < m; k += kWave) a.yq[qo + k] = nan;
+                if (a.status && lane == 0) a.status[i] = kStatusOrder;
+            }
+            return;
+        }
+        if (reporter && a.status && lane == 0) a.status[i] = kStatusOk;
+        if (it.s == 0 && a.ypp) {
+            const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+            for (int j = j0 + lane; j < jend; j += kWave) a.ypp[ko + j] = sm.so[j - rs];
+        }
+        if (it.S == 0) return;
     }
-    if (reporter && a.status && lane == 0) a.status[i] = kStatusOk;
     const int lo = max(rs - 1, 0);
-    if (it.s == 0 && a.ypp) {
-        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
-        for (int j = j0 + lane; j < jend; j += kWave) a.ypp[ko + j] = sm.so[j - rs];
-    }
-    if (it.S == 0) return;
-    for (int t = j0 + lane; t < j1; t += kWave) {
-        const double ba = sm.sx[t + 1 - lo] - sm.sx[t - lo];
-        sm.ib[t - j0] = IntervalConst{1.0 / ba, ba * ba};
-    }
-    wave_sync();
+    for (int t = j0 + lane; t < j1; t += kWave) sm.inv[t - j0] = 1.0 / (sm.sx[t + 1 - lo] - sm.sx[t - lo]);
 
     // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the
     // first block); this item takes share s of S of them.
@@ -103,79 +166,131 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
     const int64_t k1 = k0 + per + ((int64_t)it.s < rem ? 1 : 0);
     if (k0 >= k1) return;
     double* __restrict__ out = a.yq + qo;
+    const double dl = (double)lane;
+    // intervals of the share's first and last query: j0 plus the interior
+    // knots of the block below each
+    int t0, t1;
+    {
+        const double qa = uniform_query(x0, xl, h, m, k0);
+        const double qb = uniform_query(x0, xl, h, m, k1 - 1);
+        int ca = 0, cb = 0;
+        for (int j = j0 + 1 + lane; j - lane < j1; j += kWave) {
+            const double xj = j < j1 ? sm.sx[j - lo] : 0.0;
+            ca += __popcll(__ballot(j < j1 && xj < qa));
+            cb += __popcll(__ballot(j < j1 && xj < qb));
+        }
+        t0 = j0 + ca;
+        t1 = j0 + cb;
+    }
+    const int nt = t1 - t0 + 1;
+    wave_sync();
 
-    if (len < 4 * (int64_t)(j1 - j0)) {
-        // sparse: every query searches the block's knots
-        for (int64_t k = k0 + lane; k < k1; k += kWave) {
-            const double q = uniform_query(x0, xl, h, m, k);
-            const int t = (int)lower_bound_idx(sm.sx, j0 + 1 - lo, j1 - 1 - j0, q) + lo - 1;
-            const IntervalConst c = sm.ib[t - j0];
-            out[k] = newint(q, sm.sx[t - lo], sm.sx[t + 1 - lo], sm.sy[t - lo], sm.sy[t + 1 - lo],
-                            sm.so[t - rs], sm.so[t + 1 - rs], c.inv);
+    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
+        // many queries per interval: interval by interval, its constants in
+        // registers, up to 64 queries of one interval per store.  bq[i] is the
+        // first query of interval t0 + i, less k0.
+        for (int c = lane; c <= nt; c += kWave) {
+            int64_t v;
+            if (c == 0) v = k0;
+            else if (c == nt) v = k1;
+            else v = min(max(first_query_above_r(x0, xl, h, rh, m, sm.sx[t0 + c - lo]), k0), k1);
+            sm.bq[c] = (int32_t)(v - k0);
+        }
+        wave_sync();
+        const double kl0 = (double)k0 + dl;
+        double* __restrict__ o = out + k0 + lane;
+        for (int c = 0; c < nt; ++c) {
+            const int t = t0 + c;
+            const int ks = sm.bq[c];
+            const int ke = sm.bq[c + 1];
+            if (ks >= ke) continue;
+            const double av = sm.sx[t - lo];
+            const double bv = sm.sx[t + 1 - lo];
+            const double u = sm.sy[t - lo];
+            const double v = sm.sy[t + 1 - lo];
+            const double up = sm.so[t - rs];
+            const double vp = sm.so[t + 1 - rs];
+            const double inv = sm.inv[t - j0];
+            const double ba = bv - av;
+            const double ba2 = ba * ba;
+            // kr = k0 + lane + r is the query index k exactly (integers below
+            // 2^53 in double), so x0 + kr*h, one multiply then one add, is the
+            // position uniform_query(.., k) bit for bit (query m-1 aside,
+            // which is x[n-1] itself and is patched below)
+            double kr = kl0 + (double)ks;
+            double* __restrict__ ob = o + ks;
+            int r = ks;
+            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
+                double q0, q1;
+                {
+#pragma clang fp contract(off)
+                    const double s0 = kr * h;
+                    const double s1 = (kr + (double)kWave) * h;
+                    q0 = x0 + s0;
+                    q1 = x0 + s1;
+                }
+                // a6: newint with the interval's 1/(b - a) and (b - a)^2
+                const double xa0 = q0 - av, bx0 = bv - q0;
+                const double xa1 = q1 - av, bx1 = bv - q1;
+                const double l0 = xa0 * v + bx0 * u;
+                const double l1 = xa1 * v + bx1 * u;
+                const double c0 = (xa0 * xa0 - ba2) * xa0 * vp + (bx0 * bx0 - ba2) * bx0 * up;
+                const double c1 = (xa1 * xa1 - ba2) * xa1 * vp + (bx1 * bx1 - ba2) * bx1 * up;
+                ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
+                ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                ob += 2 * kWave;
+                kr += (double)(2 * kWave);
+            }
+            for (; r < ke; r += kWave) {
+                double q;
+                {
+#pragma clang fp contract(off)
+                    const double st = kr * h;
+                    q = x0 + st;
+                }
+                const double xa = q - av, bx = bv - q;
+                const double l = xa * v + bx * u;
+                const double cc = (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
+                if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
+                ob += kWave;
+                kr += (double)kWave;
+            }
+        }
+        if (k1 == m && m > 1 && lane == 0) {
+            // query m-1 is x[n-1] itself (for m > 1), in interval t1
+            const int t = t1;
+            out[m - 1] = newint(xl, sm.sx[t - lo], sm.sx[t + 1 - lo], sm.sy[t - lo], sm.sy[t + 1 - lo],
+                                sm.so[t - rs], sm.so[t + 1 - rs], sm.inv[t - j0]);
         }
         return;
     }
-    // dense: 64 consecutive queries at a time; the wavefront carries the
-    // interval t of its next query and the first query knext of interval
-    // t + 1, and each lane moves past the boundaries its own query crossed.
-    int t = j0;
-    if (k0 > ka) {
-        // interval of query k0: j0 plus the interior knots of the block below it
-        const double q0 = uniform_query(x0, xl, h, m, k0);
-        int cnt = 0;
-        for (int j = j0 + 1 + lane; j - lane < j1; j += kWave)
-            cnt += __popcll(__ballot(j < j1 && sm.sx[j - lo] < q0));
-        t = j0 + cnt;
-    }
-    int64_t knext = (t + 1 < j1) ? first_query_above_r(x0, xl, h, rh, m, sm.sx[t + 1 - lo]) : k1;
-    const double dl = (double)lane;
+    // fewer queries per interval: 64 consecutive queries at a time; each lane
+    // finds its own interval from the wavefront's current one (the knots of
+    // the touched intervals are few per chunk)
+    int t = t0;
     for (int64_t kc = k0; kc < k1; kc += kWave) {
         const int64_t k = kc + lane;
-        const int64_t klast = min(kc + kWave - 1, k1 - 1);
+        const bool live = k < k1;
+        const double q = uniform_query(x0, xl, h, m, live ? k : k1 - 1);
         int tl = t;
-        while (knext <= klast) {
-            ++t;
-            tl = (k >= knext) ? t : tl;
-            knext = (t + 1 < j1) ? first_query_above_r(x0, xl, h, rh, m, sm.sx[t + 1 - lo]) : k1;
-        }
-        if (k < k1) {
-            double q;
-            {
-#pragma clang fp contract(off)
-                // (double)kc + lane is (double)k exactly: the position equals
-                // uniform_query(.., k) bit for bit
-                const double step = ((double)kc + dl) * h;
-                q = x0 + step;
-            }
-            q = (k >= m - 1) ? xl : q;
-            q = (k <= 0) ? x0 : q;
-            const IntervalConst c = sm.ib[tl - j0];
-            const double av = sm.sx[tl - lo];
-            const double bv = sm.sx[tl + 1 - lo];
-            // a6: newint with the interval's 1/(b - a) and (b - a)^2
-            const double xa = q - av;
-            const double bx = bv - q;
-            const double lower = xa * sm.sy[tl + 1 - lo] + bx * sm.sy[tl - lo];
-            const double C = (xa * xa - c.ba2) * xa * sm.so[tl + 1 - rs];
-            const double D = (bx * bx - c.ba2) * bx * sm.so[tl - rs];
-            out[k] = (lower + (1.0 / 6.0) * (C + D)) * c.inv;
+        while (tl + 1 <= t1 && sm.sx[tl + 1 - lo] < q) ++tl;
+        t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
+        if (live) {
+            out[k] = newint(q, sm.sx[tl - lo], sm.sx[tl + 1 - lo], sm.sy[tl - lo], sm.sy[tl + 1 - lo],
+                            sm.so[tl - rs], sm.so[tl + 1 - rs], sm.inv[tl - j0]);
         }
     }
 }
 
-template <int CH, int WPG>
+template <int CH, int WPG, bool BUILD>
 __global__ __launch_bounds__(WPG * kWave) void wave_items_kernel(BatchDevArgs a) {
     __shared__ WaveSmem<CH> smem[WPG];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * WPG;
     for (int64_t w = (int64_t)blockIdx.x * WPG + wid; w < a.n_witems; w += stride)
-        run_wave_item<CH>(a, a.witems[w], smem[wid], lane);
+        run_wave_item<CH, BUILD>(a, a.witems[w], smem[wid], lane);
 }
-
-// ---------------------------------------------------------------------------
-// Host side.
-// ---------------------------------------------------------------------------
 
 static int wave_ch_for(int64_t max_n) {
     if (max_n <= 64) return 1;
@@ -185,22 +300,22 @@ static int wave_ch_for(int64_t max_n) {
     return kWaveMaxCH;
 }
 
-template <int CH, int WPG>
+template <int CH, int WPG, bool BUILD>
 static int launch_waves(const BatchDevArgs& a, int grid_per_cu, int num_cu, hipStream_t s) {
     const int64_t groups = (a.n_witems + WPG - 1) / WPG;
     int64_t grid = groups;
     if (grid_per_cu > 0) grid = std::min<int64_t>(groups, (int64_t)num_cu * grid_per_cu);
     if (grid < 1) return SOLVE_OK;
-    wave_items_kernel<CH, WPG><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
+    wave_items_kernel<CH, WPG, BUILD><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
     return SOLVE_OK;
 }
 
-template <int CH>
+template <int CH, bool BUILD>
 static int launch_waves_ch(const BatchDevArgs& a, const spline_tuning& t, int num_cu, hipStream_t s) {
     switch (t.block) {
-        case 64: return launch_waves<CH, 1>(a, t.grid_per_cu, num_cu, s);
-        case 128: return launch_waves<CH, 2>(a, t.grid_per_cu, num_cu, s);
-        case 256: return launch_waves<CH, 4>(a, t.grid_per_cu, num_cu, s);
+        case 64: return launch_waves<CH, 1, BUILD>(a, t.grid_per_cu, num_cu, s);
+        case 128: return launch_waves<CH, 2, BUILD>(a, t.grid_per_cu, num_cu, s);
+        case 256: return launch_waves<CH, 4, BUILD>(a, t.grid_per_cu, num_cu, s);
         default: return SOLVE_E_ARG;
     }
 }
@@ -215,8 +330,8 @@ spline_tuning default_tuning() {
 }
 
 bool valid_tuning(const spline_tuning& t) {
-    return t.fused == 1 && (t.block == 64 || t.block == 128 || t.block == 256) && t.queries_per_tile >= 64 &&
-           t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
+    return (t.fused == 1 || t.fused == 2) && (t.block == 64 || t.block == 128 || t.block == 256) &&
+           t.queries_per_tile >= 64 && t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
 }
 
 Batch::~Batch() { (void)hipFree(d_tables_); }
@@ -237,14 +352,27 @@ int Batch::ensure(void** p, size_t* cap, size_t bytes) {
 }
 
 void Batch::make_tables() {
-    // wave items: whole curves when they fit one wavefront's rows, else knot
-    // blocks with halos; shares of at most about queries_per_tile queries
+    // phase 1: the short curves, longest first
+    lane_.clear();
+    lane_max_n_ = 0;
+    for (int64_t i = 0; tuning_.fused == 2 && i < count_; ++i) {
+        if (n_[i] <= kLaneBuildMaxN) {
+            lane_.push_back((int32_t)i);
+            lane_max_n_ = std::max(lane_max_n_, n_[i]);
+        }
+    }
+    std::stable_sort(lane_.begin(), lane_.end(), [&](int32_t p, int32_t q) { return n_[p] > n_[q]; });
+    // phase 2: whole curves when built by lanes or when they fit one
+    // wavefront's rows, else knot blocks with halos; shares of at most about
+    // queries_per_tile queries
     witems_.clear();
     const int rows = wave_ch_ * kWave;
     const int64_t cap = tuning_.queries_per_tile;
     std::vector<double> cost;
     for (int64_t i = 0; i < count_; ++i) {
         const int64_t n = n_[i];
+        const bool lane_built = tuning_.fused == 2 && n <= kLaneBuildMaxN;
+        if (lane_built && !uniform_[i]) continue;  // y'' only: phase 1 does it all
         const int bk = (n <= rows) ? (int)(n - 1) : kWaveBlock;
         for (int64_t j0 = 0; j0 < n - 1; j0 += bk) {
             const int64_t j1 = std::min<int64_t>(j0 + bk, n - 1);
@@ -257,9 +385,21 @@ void Batch::make_tables() {
                 S = std::max<int64_t>(1, (int64_t)std::ceil(est / (double)cap));
             }
             for (int64_t s = 0; s < std::max<int64_t>(S, 1); ++s) {
-                witems_.push_back(WaveItem{(int32_t)i, (int16_t)j0, (int16_t)j1, (int32_t)s, (int32_t)S});
-                // a row of the build costs about as much as 8 queries
-                cost.push_back(8.0 * (double)span + (S ? est / (double)S : 0.0));
+                WaveItem w;
+                w.ko = koff_[i];
+                w.qo = qoff_[i];
+                w.m = m_[i];
+                w.inst = (int32_t)i;
+                w.n = (int32_t)n;
+                w.j0 = (int16_t)j0;
+                w.j1 = (int16_t)j1;
+                w.s = (int32_t)s;
+                w.S = (int32_t)S;
+                w.pad = 0;
+                witems_.push_back(w);
+                // staging a knot costs about as much as a query, a row of a
+                // solve about 8
+                cost.push_back((lane_built ? 1.0 : 8.0) * (double)span + (S ? est / (double)S : 0.0));
             }
         }
     }
@@ -281,6 +421,8 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
     if (koff[0] != 0 || qoff[0] != 0) return SOLVE_E_ARG;
     n_.assign(count, 0);
     m_.assign(count, 0);
+    koff_.assign(koff, koff + count + 1);
+    qoff_.assign(qoff, qoff + count + 1);
     uniform_.assign(count, 1);
     max_n_ = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -309,15 +451,20 @@ int Batch::retile(const spline_tuning& t) {
     return ensure(&d_tables_, &cap_tables_, table_bytes());
 }
 
-size_t Batch::table_bytes() const { return witems_.size() * sizeof(WaveItem); }
+size_t Batch::offset_lane() const { return (witems_.size() * sizeof(WaveItem) + 255) & ~(size_t)255; }
+size_t Batch::table_bytes() const { return offset_lane() + lane_.size() * sizeof(int32_t); }
 
 void Batch::write_tables(void* dst) const {
-    if (!witems_.empty()) std::memcpy(dst, witems_.data(), table_bytes());
+    if (!witems_.empty()) std::memcpy(dst, witems_.data(), witems_.size() * sizeof(WaveItem));
+    if (!lane_.empty()) std::memcpy((char*)dst + offset_lane(), lane_.data(), lane_.size() * sizeof(int32_t));
 }
 
 int Batch::upload(hipStream_t s) {
-    if (!witems_.empty() &&
-        hipMemcpyAsync(d_tables_, witems_.data(), table_bytes(), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (!witems_.empty() && hipMemcpyAsync(d_tables_, witems_.data(), witems_.size() * sizeof(WaveItem),
+                                           hipMemcpyHostToDevice, s) != hipSuccess)
+        return SOLVE_E_DEVICE;
+    if (!lane_.empty() && hipMemcpyAsync((char*)d_tables_ + offset_lane(), lane_.data(),
+                                         lane_.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return SOLVE_E_DEVICE;
     return SOLVE_OK;
 }
@@ -343,14 +490,34 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     a.status = status;
     a.witems = (const WaveItem*)tables;
     a.n_witems = (int64_t)witems_.size();
+    a.lane_curves = (const int32_t*)((const char*)tables + offset_lane());
+    a.n_lane = (int64_t)lane_.size();
+    if (a.n_lane > 0) {
+        const unsigned g = (unsigned)((a.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
+        const int64_t lane_max = lane_max_n_;
+        if (lane_max <= kGroupLanes * 4) group_build_kernel<4><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
+        else if (lane_max <= kGroupLanes * 9) group_build_kernel<9><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
+        else group_build_kernel<16><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
+    }
+    a.prebuilt_max_n = (tuning_.fused == 2) ? kLaneBuildMaxN : 0;
     int rc = SOLVE_E_ARG;
-    switch (wave_ch_) {
-        case 1: rc = launch_waves_ch<1>(a, tuning_, num_cu_, s); break;
-        case 2: rc = launch_waves_ch<2>(a, tuning_, num_cu_, s); break;
-        case 3: rc = launch_waves_ch<3>(a, tuning_, num_cu_, s); break;
-        case 4: rc = launch_waves_ch<4>(a, tuning_, num_cu_, s); break;
-        case kWaveMaxCH: rc = launch_waves_ch<kWaveMaxCH>(a, tuning_, num_cu_, s); break;
-        default: break;
+    if (tuning_.fused == 2 && max_n_ <= kLaneBuildMaxN) {
+        switch (wave_ch_) {
+            case 1: rc = launch_waves_ch<1, false>(a, tuning_, num_cu_, s); break;
+            case 2: rc = launch_waves_ch<2, false>(a, tuning_, num_cu_, s); break;
+            case 3: rc = launch_waves_ch<3, false>(a, tuning_, num_cu_, s); break;
+            case 4: rc = launch_waves_ch<4, false>(a, tuning_, num_cu_, s); break;
+            default: break;
+        }
+    } else {
+        switch (wave_ch_) {
+            case 1: rc = launch_waves_ch<1, true>(a, tuning_, num_cu_, s); break;
+            case 2: rc = launch_waves_ch<2, true>(a, tuning_, num_cu_, s); break;
+            case 3: rc = launch_waves_ch<3, true>(a, tuning_, num_cu_, s); break;
+            case 4: rc = launch_waves_ch<4, true>(a, tuning_, num_cu_, s); break;
+            case kWaveMaxCH: rc = launch_waves_ch<kWaveMaxCH, true>(a, tuning_, num_cu_, s); break;
+            default: break;
+        }
     }
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
@@ -551,12 +718,13 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
             return SOLVE_OK;
         }
     }
-    // wavefronts per workgroup x query share x (one item per wavefront, or
-    // persistent wavefronts)
+    // one or two launches x wavefronts per workgroup x query share x (one
+    // item per wavefront, or persistent wavefronts)
     std::vector<spline_tuning> cands;
-    for (int block : {64, 128, 256})
-        for (int cap : {1024, 2048, 4096, 8192})
-            for (int gpc : {0, 16}) cands.push_back(spline_tuning{block, cap, gpc, 1});
+    for (int fused : {1, 2})
+        for (int block : {64, 256})
+            for (int cap : {2048, 4096, 8192})
+                for (int gpc : {0, 16}) cands.push_back(spline_tuning{block, cap, gpc, fused});
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;
     hipEvent_t e0, e1;

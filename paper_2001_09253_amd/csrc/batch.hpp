@@ -1,14 +1,18 @@
-// Batched form of the spline path: many curves in CSR layout, in one launch.
+// Batched form of the spline path: many curves in CSR layout.
 //
-// A list of wave items, each run by one wavefront from start to end with no
-// waiting on any other wavefront.  A wave
-// item is (curve, knot block, query share): the wavefront solves the block's
-// span for y'' exactly in its own LDS -- the whole curve when it fits one
+// Phase 1 (only if the batch holds curves of at most kLaneBuildMaxN knots):
+// 16 lanes per such curve (four curves per wavefront) solve it for y'': each
+// lane runs the paper's sweeps over a chunk of rows and the chunks are joined
+// by short scans.  Phase 2: a list of wave items, each run by
+// one wavefront from start to end with no waiting on any other wavefront.  A
+// wave item is (curve, knot block, query share): the wavefront stages the
+// block's knots, values and y'' in its own LDS -- solving the span itself for
+// curves past kLaneBuildMaxN knots: the whole curve when it fits one
 // wavefront's rows, else the block of intervals plus a halo of rows on either
 // side -- and then evaluates its share of the uniform queries that fall in the
-// block.  Curves with many queries are cut into several shares, each solving
-// the same small span again, so that no wavefront holds far more work than
-// the average.  Items are ordered by decreasing work.
+// block.  Curves with many queries are cut into several shares so that no
+// wavefront holds far more work than the average.  Items are ordered by
+// decreasing work.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,17 +24,23 @@
 
 namespace spl {
 
+constexpr int kLaneBuildMaxN = 256;  // curves up to this many knots are built in phase 1
 constexpr int kBatchHalo = 128;      // halo rows on either side of a knot block
 constexpr int kWaveMaxCH = 8;        // rows per lane of the largest wave span
 constexpr int kWaveSpanMax = 64 * kWaveMaxCH;
 constexpr int kWaveBlock = kWaveSpanMax - 1 - 2 * kBatchHalo;  // intervals per knot block
 
-struct WaveItem {
+struct alignas(16) WaveItem {
+    int64_t ko;     // first knot of the curve
+    int64_t qo;     // first output of the curve
+    int64_t m;      // its query count
     int32_t inst;   // curve
+    int32_t n;      // its knot count
     int16_t j0;     // intervals [j0, j1) of the curve
     int16_t j1;
     int32_t s;      // share s of S of the block's queries (S = 0: y'' only)
     int32_t S;
+    int32_t pad;
 };
 
 struct BatchDevArgs {
@@ -45,6 +55,9 @@ struct BatchDevArgs {
     int32_t* status;
     const WaveItem* witems;
     int64_t n_witems;
+    const int32_t* lane_curves;  // curves built in phase 1, longest first
+    int64_t n_lane;
+    int64_t prebuilt_max_n;      // curves up to this length were built in phase 1 (0: none)
 };
 
 // Host side of a batch: the work tables and the device buffers that hold them.
@@ -98,9 +111,12 @@ private:
     int wave_ch_ = 1;
     uint32_t precision_ = 0;
     spline_tuning tuning_{};
-    std::vector<int64_t> n_, m_;
+    std::vector<int64_t> n_, m_, koff_, qoff_;
     std::vector<uint8_t> uniform_;
     std::vector<WaveItem> witems_;
+    std::vector<int32_t> lane_;
+    int64_t lane_max_n_ = 0;
+    size_t offset_lane() const;
     void* d_tables_ = nullptr;
     size_t cap_tables_ = 0;
     int num_cu_ = 0;

@@ -340,6 +340,46 @@ __device__ __forceinline__ Bwd wave_excl_suffix_bwd(Bwd v, int lane, Bwd* incl_o
     return lane == kWave - 1 ? bwd_identity() : ex;
 }
 
+// The same scans over groups of G = 16 lanes (one DPP row each): every row
+// of 16 lanes scans its own maps, with the identity shifted in at the row's
+// ends, so four curves share a wavefront without mixing.
+constexpr int kDppRowShl1 = 0x101, kDppRowShl2 = 0x102, kDppRowShl4 = 0x104, kDppRowShl8 = 0x108;
+
+template <int CTRL>
+__device__ __forceinline__ Bwd dpp_bwd(const Bwd& v) {
+    return Bwd{dpp_f64<CTRL, 0xf>(1.0, v.K), dpp_f64<CTRL, 0xf>(0.0, v.H)};
+}
+
+template <bool NORM, int G>
+__device__ __forceinline__ Fwd group_excl_prefix_fwd(Fwd v, Fwd* incl_out) {
+    if constexpr (G == kWave) {
+        return wave_excl_prefix_fwd_dpp<NORM>(v, incl_out);
+    } else {
+        static_assert(G == 16, "groups are whole wavefronts or DPP rows");
+        v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr1, 0xf>(v));
+        v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr2, 0xf>(v));
+        v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr4, 0xf>(v));
+        v = fwd_comp<NORM>(v, dpp_fwd<kDppRowShr8, 0xf>(v));
+        *incl_out = v;
+        return dpp_fwd<kDppRowShr1, 0xf>(v);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ Bwd group_excl_suffix_bwd(Bwd v, int lane, Bwd* incl_out) {
+    if constexpr (G == kWave) {
+        return wave_excl_suffix_bwd(v, lane, incl_out);
+    } else {
+        static_assert(G == 16, "groups are whole wavefronts or DPP rows");
+        v = bwd_compose(v, dpp_bwd<kDppRowShl1>(v));
+        v = bwd_compose(v, dpp_bwd<kDppRowShl2>(v));
+        v = bwd_compose(v, dpp_bwd<kDppRowShl4>(v));
+        v = bwd_compose(v, dpp_bwd<kDppRowShl8>(v));
+        *incl_out = v;
+        return dpp_bwd<kDppRowShl1>(v);
+    }
+}
+
 // Cross-workgroup signalling.  On a multi-XCD device an agent-scope acquire
 // or release maintains the XCD's L2 (write back / invalidate), so a poll loop
 // must not acquire on every iteration: it polls with relaxed atomic loads and
@@ -374,9 +414,16 @@ __device__ __forceinline__ void group_sync() {
     if constexpr (WAVE_ONLY) wave_sync(); else __syncthreads();
 }
 
-template <bool WAVE_ONLY>
+template <bool WAVE_ONLY, int G = kWave>
 __device__ __forceinline__ bool group_any(bool p) {
-    if constexpr (WAVE_ONLY) return __ballot(p) != 0ull; else return __syncthreads_or(p) != 0;
+    if constexpr (!WAVE_ONLY) {
+        return __syncthreads_or(p) != 0;
+    } else if constexpr (G == kWave) {
+        return __ballot(p) != 0ull;
+    } else {
+        const int base = (int)(__lane_id() & ~(unsigned)(G - 1));
+        return ((__ballot(p) >> base) & ((1ull << G) - 1)) != 0ull;
+    }
 }
 
 // Row j of the system in the paper's form, from the widths of the intervals on
@@ -433,7 +480,7 @@ __device__ __forceinline__ bool build_span(const double* __restrict__ x, const d
                            double sd, double ed, double* __restrict__ ypp, int32_t* __restrict__ status,
                            double* lds, Fwd* lds_f, Bwd* lds_b, const Cross& cross, int tid,
                            double* lds_y = nullptr, double* lds_out = nullptr) {
-    static_assert(NT % kWave == 0, "group must be whole wavefronts");
+    static_assert(NT % kWave == 0 || (WAVE_ONLY && NT == 16), "group must be whole wavefronts or a DPP row");
     constexpr int NW = NT / kWave;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -475,7 +522,7 @@ __device__ __forceinline__ bool build_span(const double* __restrict__ x, const d
             }
         }
     }
-    bad = group_any<WAVE_ONLY>(bad);
+    bad = group_any<WAVE_ONLY, (NT < kWave ? NT : kWave)>(bad);
     cross.publish_bad(bad);
 
     // a1/a2: slopes and right-hand sides (y staged through the same LDS
@@ -527,7 +574,7 @@ __device__ __forceinline__ bool build_span(const double* __restrict__ x, const d
     // entries stay within 1.5^rows and 0.375^rows of 1, which the caller
     // keeps inside the double range (a few hundred rows).
     Fwd incl;
-    Fwd pre = wave_excl_prefix_fwd_dpp<NORM>(acc, &incl);
+    Fwd pre = group_excl_prefix_fwd<NORM, (NT < kWave ? NT : kWave)>(acc, &incl);
     if constexpr (!WAVE_ONLY) {
         if (lane == kWave - 1) lds_f[wid] = incl;
         __syncthreads();
@@ -577,7 +624,7 @@ __device__ __forceinline__ bool build_span(const double* __restrict__ x, const d
         if (i < cnt) bacc = bwd_compose(Bwd{-w[i], d[i]}, bacc);
     }
     Bwd bincl;
-    Bwd suf = wave_excl_suffix_bwd(bacc, lane, &bincl);
+    Bwd suf = group_excl_suffix_bwd<(NT < kWave ? NT : kWave)>(bacc, lane, &bincl);
     if constexpr (!WAVE_ONLY) {
         if (lane == 0) lds_b[wid] = bincl;
         __syncthreads();
