@@ -207,6 +207,26 @@ def bench_batched(args, precision):
                      "traffic": measured_traffic("wave_items" if best.fused else "build+eval", wl),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": launch_ms},
     }
+    if precision != api.FP64:
+        # per-instance error of the mixed path against the FP64 oracle, in
+        # the scaled metric |g - o| / (|o| + max|o| of the instance)
+        import oracle
+        o_yq, o_ypp, _, _ = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
+        yq = bufs["yq"].cpu().numpy()
+        ypp = bufs["ypp"].cpu().numpy()
+
+        def scaled(g, o):
+            sc = np.max(np.abs(o)) if o.size else 0.0
+            return float(np.max(np.abs(g - o) / (np.abs(o) + sc + 1e-300))) if o.size else 0.0
+
+        e_yq = np.array([scaled(yq[b.qoff[i]:b.qoff[i + 1]], o_yq[b.qoff[i]:b.qoff[i + 1]]) for i in range(b.count)])
+        e_ypp = np.array([scaled(ypp[b.koff[i]:b.koff[i + 1]], o_ypp[b.koff[i]:b.koff[i + 1]])
+                          for i in range(b.count)])
+        out["error_vs_oracle"] = {
+            "metric": "per instance max |g - o| / (|o| + max|o|)",
+            "yq": {"max": float(e_yq.max()), "p50": float(np.median(e_yq)), "p99": float(np.percentile(e_yq, 99))},
+            "ypp": {"max": float(e_ypp.max()), "p50": float(np.median(e_ypp)),
+                    "p99": float(np.percentile(e_ypp, 99))}}
     if not args.no_cpu_baseline:
         import oracle
         sub = 512

@@ -41,9 +41,132 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void group_build_ker
     const int n = has ? (int)(a.koff[i + 1] - ko) : 0;
     // spans of at most 256 rows: the per-row scaling alone keeps the scan's
     // entries inside the double range, so the scan does not normalise
-    build_span<kGroupLanes, CH, true, SoloGroup, false>(
+    const bool bad = build_span<kGroupLanes, CH, true, SoloGroup, false>(
         a.x + ko, a.y + ko, n, 0, n, has ? a.sd[i] : 0.0, has ? a.ed[i] : 0.0, has ? a.ypp + ko : nullptr,
         (has && a.status) ? a.status + i : nullptr, lds[grp], nullptr, nullptr, SoloGroup{}, gl);
+    if (has && gl == 0) a.bad[i] = bad ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1 in mixed precision (SOLVE_FP32_REFINE): one wavefront per curve.
+// The rows of a1-a2 are formed in FP64 (all lanes); the paper's forward
+// elimination and back substitution run in FP32 over them (lane 0); then
+// REFINE times the FP64 residual d - T y'' of the same rows is formed (all
+// lanes) and the FP32 sweeps solve for its correction (lane 0), which is added
+// in FP64: iterative refinement with an FP32 solver.
+// ---------------------------------------------------------------------------
+constexpr int kRefineSteps = 2;
+
+template <int NCAP>
+struct MixedSmem {
+    double sx[NCAP], sy[NCAP];
+    double d[NCAP];       // right-hand sides (FP64)
+    double yh[NCAP];      // the current y'' (FP64)
+    double r[NCAP];       // residual, then correction
+    float af[NCAP], bf[NCAP], cf[NCAP];  // rows in FP32
+    float cp[NCAP], rf[NCAP];            // c' and 1/(b - a c') of the FP32 sweep
+};
+
+template <int NCAP>
+__global__ __launch_bounds__(kWave) void mixed_build_kernel(BatchDevArgs a) {
+    __shared__ MixedSmem<NCAP> sm;
+    const int lane = threadIdx.x;
+    const int64_t slot = blockIdx.x;
+    const int i = a.lane_curves[slot];
+    const int64_t ko = a.koff[i];
+    const int n = (int)(a.koff[i + 1] - ko);
+    const double sd = a.sd[i];
+    const double ed = a.ed[i];
+    const bool nat_s = natural_end(sd);
+    const bool nat_e = natural_end(ed);
+    for (int j = lane; j < n; j += kWave) {
+        sm.sx[j] = a.x[ko + j];
+        sm.sy[j] = a.y[ko + j];
+    }
+    wave_sync();
+    bool b = false;
+    for (int j = 1 + lane; j < n; j += kWave) b |= !(sm.sx[j] > sm.sx[j - 1]);
+    const bool bad = __ballot(b) != 0ull;
+    if (lane == 0) {
+        a.bad[i] = bad ? 1 : 0;
+        if (a.status) a.status[i] = bad ? kStatusOrder : kStatusOk;
+    }
+    if (bad) {
+        const double nan = __builtin_nan("");
+        for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = nan;
+        return;
+    }
+    // rows (FP64): a_j = x_j - x_{j-1}, c_j = x_{j+1} - x_j, b_j = 2(a_j + c_j),
+    // d_j = 6(s_j - s_{j-1}); the end rows as the paper's clamped or natural ends
+    for (int j = lane; j < n; j += kWave) {
+        const double wa = j > 0 ? sm.sx[j] - sm.sx[j - 1] : 0.0;
+        const double wc = j + 1 < n ? sm.sx[j + 1] - sm.sx[j] : 0.0;
+        const double sa = j > 0 ? (sm.sy[j] - sm.sy[j - 1]) / wa : 0.0;
+        const double sc = j + 1 < n ? (sm.sy[j + 1] - sm.sy[j]) / wc : 0.0;
+        double ra = wa, rb = 2.0 * (wa + wc), rc = wc, rd;
+        if (j == 0) rd = 6.0 * (sc - sd);
+        else if (j == n - 1) rd = 6.0 * (ed - sa);
+        else rd = 6.0 * (sc - sa);
+        if ((j == 0 && nat_s) || (j == n - 1 && nat_e)) {
+            ra = 0.0;
+            rb = 1.0;
+            rc = 0.0;
+            rd = 0.0;
+        }
+        sm.af[j] = (float)ra;
+        sm.bf[j] = (float)rb;
+        sm.cf[j] = (float)rc;
+        sm.d[j] = rd;
+        sm.r[j] = rd;
+    }
+    wave_sync();
+    for (int step = 0; step <= kRefineSteps; ++step) {
+        if (lane == 0) {
+            // FP32 forward elimination (the matrix is the same every step, so
+            // c' and the pivots are formed once) and back substitution of r
+            float dp = 0.0f;
+            float cpv = 0.0f;
+            for (int j = 0; j < n; ++j) {
+                float rj;
+                if (step == 0) {
+                    rj = 1.0f / (sm.bf[j] - sm.af[j] * cpv);
+                    cpv = sm.cf[j] * rj;
+                    sm.cp[j] = cpv;
+                    sm.rf[j] = rj;
+                } else {
+                    rj = sm.rf[j];
+                }
+                dp = ((float)sm.r[j] - sm.af[j] * dp) * rj;
+                sm.r[j] = dp;
+            }
+            float yv = dp;
+            for (int j = n - 2; j >= 0; --j) {
+                yv = (float)sm.r[j] - sm.cp[j] * yv;
+                sm.r[j] = yv;
+            }
+        }
+        wave_sync();
+        // add the correction (FP64), then form the next residual d - T y''
+        for (int j = lane; j < n; j += kWave) sm.yh[j] = (step == 0 ? 0.0 : sm.yh[j]) + sm.r[j];
+        wave_sync();
+        if (step == kRefineSteps) break;
+        for (int j = lane; j < n; j += kWave) {
+            const double wa = j > 0 ? sm.sx[j] - sm.sx[j - 1] : 0.0;
+            const double wc = j + 1 < n ? sm.sx[j + 1] - sm.sx[j] : 0.0;
+            double ra = wa, rb = 2.0 * (wa + wc), rc = wc;
+            if ((j == 0 && nat_s) || (j == n - 1 && nat_e)) {
+                ra = 0.0;
+                rb = 1.0;
+                rc = 0.0;
+            }
+            double t = rb * sm.yh[j];
+            if (j > 0) t += ra * sm.yh[j - 1];
+            if (j + 1 < n) t += rc * sm.yh[j + 1];
+            sm.r[j] = sm.d[j] - t;
+        }
+        wave_sync();
+    }
+    for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = sm.yh[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -64,10 +187,22 @@ struct WaveSmem {
     int32_t bq[kRows + 1];
 };
 
+// The cubic part of newint, (xa^2 - ba^2) xa y''_b + (bx^2 - ba^2) bx y''_a,
+// in FP64, or (MIXED) in FP32 around the FP64 linear part.
+template <bool MIXED>
+__device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, double up, double vp) {
+    if constexpr (MIXED) {
+        const float xf = (float)xa, bf = (float)bx, b2 = (float)ba2;
+        return (double)((xf * xf - b2) * xf * (float)vp + (bf * bf - b2) * bf * (float)up);
+    } else {
+        return (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
+    }
+}
+
 // One wave item.  All 64 lanes of the wavefront call this.  BUILD: items of
 // curves past a.prebuilt_max_n knots solve their span here; curves up to that
 // length were built by phase 1.
-template <int CH, bool BUILD>
+template <int CH, bool BUILD, bool MIXED>
 __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem<CH>& sm, int lane) {
     const int i = it.inst;
     const int64_t ko = it.ko;
@@ -81,31 +216,9 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
     const bool reporter = j0 == 0 && it.s == 0;  // fills the outputs of a bad curve with NaN
     int rs = 0, re = n;
     if (!BUILD || n <= a.prebuilt_max_n) {
-        // y'' from phase 1: stage the whole curve (n <= 64 CH), every load
-        // issued before the first store to LDS
-        double rx[CH], ry[CH], rp[CH];
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int j = lane + c * kWave;
-            if (j < n) {
-                rx[c] = x[j];
-                ry[c] = y[j];
-                rp[c] = a.ypp[ko + j];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int j = lane + c * kWave;
-            if (j < n) {
-                sm.sx[j] = rx[c];
-                sm.sy[j] = ry[c];
-                sm.so[j] = rp[c];
-            }
-        }
-        wave_sync();
-        bool b = false;
-        for (int j = 1 + lane; j < n; j += kWave) b |= !(sm.sx[j] > sm.sx[j - 1]);
-        if (__ballot(b) != 0ull) {
+        // y'' from phase 1: stage knots lo..j1 (lo = max(j0 - 1, 0)) of the
+        // block (at most 64 CH + 1), every load issued before the first store
+        if (a.bad[i]) {
             if (reporter && it.S > 0) {
                 const double nan = __builtin_nan("");
                 for (int64_t k = lane; k < m; k += kWave) a.yq[qo + k] = nan;
@@ -113,6 +226,29 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
             return;
         }
         if (it.S == 0) return;
+        rs = j0;
+        const int lo_ = max(j0 - 1, 0);
+        const int cnt = j1 - lo_ + 1;
+        double rx[CH + 1], ry[CH + 1], rp[CH + 1];
+#pragma unroll
+        for (int c = 0; c <= CH; ++c) {
+            const int j = lane + c * kWave;
+            if (j < cnt) {
+                rx[c] = x[lo_ + j];
+                ry[c] = y[lo_ + j];
+                rp[c] = a.ypp[ko + lo_ + j];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c <= CH; ++c) {
+            const int j = lane + c * kWave;
+            if (j < cnt) {
+                sm.sx[j] = rx[c];
+                sm.sy[j] = ry[c];
+                if (lo_ + j >= rs) sm.so[lo_ + j - rs] = rp[c];
+            }
+        }
+        wave_sync();
     } else {
         // a1-a4 over the block's span, exact to rounding with the halo (the
         // dropped coupling decays by 2/3 or better per row); the whole curve
@@ -234,8 +370,8 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
                 const double xa1 = q1 - av, bx1 = bv - q1;
                 const double l0 = xa0 * v + bx0 * u;
                 const double l1 = xa1 * v + bx1 * u;
-                const double c0 = (xa0 * xa0 - ba2) * xa0 * vp + (bx0 * bx0 - ba2) * bx0 * up;
-                const double c1 = (xa1 * xa1 - ba2) * xa1 * vp + (bx1 * bx1 - ba2) * bx1 * up;
+                const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
+                const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
                 ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
                 ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
                 ob += 2 * kWave;
@@ -250,7 +386,7 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
                 }
                 const double xa = q - av, bx = bv - q;
                 const double l = xa * v + bx * u;
-                const double cc = (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
+                const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
                 if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
                 ob += kWave;
                 kr += (double)kWave;
@@ -282,14 +418,14 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
     }
 }
 
-template <int CH, int WPG, bool BUILD>
+template <int CH, int WPG, bool BUILD, bool MIXED>
 __global__ __launch_bounds__(WPG * kWave) void wave_items_kernel(BatchDevArgs a) {
     __shared__ WaveSmem<CH> smem[WPG];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * WPG;
     for (int64_t w = (int64_t)blockIdx.x * WPG + wid; w < a.n_witems; w += stride)
-        run_wave_item<CH, BUILD>(a, a.witems[w], smem[wid], lane);
+        run_wave_item<CH, BUILD, MIXED>(a, a.witems[w], smem[wid], lane);
 }
 
 static int wave_ch_for(int64_t max_n) {
@@ -300,22 +436,34 @@ static int wave_ch_for(int64_t max_n) {
     return kWaveMaxCH;
 }
 
-template <int CH, int WPG, bool BUILD>
+template <int CH, int WPG, bool BUILD, bool MIXED>
 static int launch_waves(const BatchDevArgs& a, int grid_per_cu, int num_cu, hipStream_t s) {
     const int64_t groups = (a.n_witems + WPG - 1) / WPG;
     int64_t grid = groups;
     if (grid_per_cu > 0) grid = std::min<int64_t>(groups, (int64_t)num_cu * grid_per_cu);
     if (grid < 1) return SOLVE_OK;
-    wave_items_kernel<CH, WPG, BUILD><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
+    wave_items_kernel<CH, WPG, BUILD, MIXED><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
     return SOLVE_OK;
 }
 
-template <int CH, bool BUILD>
+template <int CH, bool BUILD, bool MIXED>
 static int launch_waves_ch(const BatchDevArgs& a, const spline_tuning& t, int num_cu, hipStream_t s) {
     switch (t.block) {
-        case 64: return launch_waves<CH, 1, BUILD>(a, t.grid_per_cu, num_cu, s);
-        case 128: return launch_waves<CH, 2, BUILD>(a, t.grid_per_cu, num_cu, s);
-        case 256: return launch_waves<CH, 4, BUILD>(a, t.grid_per_cu, num_cu, s);
+        case 64: return launch_waves<CH, 1, BUILD, MIXED>(a, t.grid_per_cu, num_cu, s);
+        case 128: return launch_waves<CH, 2, BUILD, MIXED>(a, t.grid_per_cu, num_cu, s);
+        case 256: return launch_waves<CH, 4, BUILD, MIXED>(a, t.grid_per_cu, num_cu, s);
+        default: return SOLVE_E_ARG;
+    }
+}
+
+template <bool BUILD, bool MIXED>
+static int launch_waves_any(int ch, const BatchDevArgs& a, const spline_tuning& t, int num_cu, hipStream_t s) {
+    switch (ch) {
+        case 1: return launch_waves_ch<1, BUILD, MIXED>(a, t, num_cu, s);
+        case 2: return launch_waves_ch<2, BUILD, MIXED>(a, t, num_cu, s);
+        case 3: return launch_waves_ch<3, BUILD, MIXED>(a, t, num_cu, s);
+        case 4: return launch_waves_ch<4, BUILD, MIXED>(a, t, num_cu, s);
+        case kWaveMaxCH: return launch_waves_ch<kWaveMaxCH, BUILD, MIXED>(a, t, num_cu, s);
         default: return SOLVE_E_ARG;
     }
 }
@@ -334,7 +482,10 @@ bool valid_tuning(const spline_tuning& t) {
            t.queries_per_tile >= 64 && t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
 }
 
-Batch::~Batch() { (void)hipFree(d_tables_); }
+Batch::~Batch() {
+    (void)hipFree(d_tables_);
+    (void)hipFree(d_bad_);
+}
 
 int Batch::ensure(void** p, size_t* cap, size_t bytes) {
     if (bytes <= *cap && *p) return SOLVE_OK;
@@ -353,31 +504,36 @@ int Batch::ensure(void** p, size_t* cap, size_t bytes) {
 
 void Batch::make_tables() {
     // phase 1: the short curves, longest first
+    // (mixed precision: every curve, by the FP32 solver with FP64 refinement)
     lane_.clear();
     lane_max_n_ = 0;
-    for (int64_t i = 0; tuning_.fused == 2 && i < count_; ++i) {
-        if (n_[i] <= kLaneBuildMaxN) {
+    prebuilt_max_n_ = (precision_ == SOLVE_FP32_REFINE) ? SOLVE_MAX_N_BATCH
+                      : (tuning_.fused == 2)           ? kLaneBuildMaxN
+                                                       : 0;
+    for (int64_t i = 0; i < count_; ++i) {
+        if (n_[i] <= prebuilt_max_n_) {
             lane_.push_back((int32_t)i);
             lane_max_n_ = std::max(lane_max_n_, n_[i]);
         }
     }
     std::stable_sort(lane_.begin(), lane_.end(), [&](int32_t p, int32_t q) { return n_[p] > n_[q]; });
-    // phase 2: whole curves when built by lanes or when they fit one
-    // wavefront's rows, else knot blocks with halos; shares of at most about
-    // queries_per_tile queries
+    // phase 2: whole curves when they fit one wavefront's rows, else knot
+    // blocks (with halos when the item solves its own span); shares of at
+    // most about queries_per_tile queries
     witems_.clear();
     const int rows = wave_ch_ * kWave;
     const int64_t cap = tuning_.queries_per_tile;
     std::vector<double> cost;
     for (int64_t i = 0; i < count_; ++i) {
         const int64_t n = n_[i];
-        const bool lane_built = tuning_.fused == 2 && n <= kLaneBuildMaxN;
+        const bool lane_built = n <= prebuilt_max_n_;
         if (lane_built && !uniform_[i]) continue;  // y'' only: phase 1 does it all
-        const int bk = (n <= rows) ? (int)(n - 1) : kWaveBlock;
+        const int bk = (n <= rows) ? (int)(n - 1) : lane_built ? rows - 1 : kWaveBlock;
         for (int64_t j0 = 0; j0 < n - 1; j0 += bk) {
             const int64_t j1 = std::min<int64_t>(j0 + bk, n - 1);
-            const int64_t span = (n <= rows) ? n : std::min<int64_t>(n, j1 + 1 + kBatchHalo) -
-                                                       std::max<int64_t>(0, j0 - kBatchHalo);
+            const int64_t span = (n <= rows || lane_built) ? j1 - j0 + 1
+                                                           : std::min<int64_t>(n, j1 + 1 + kBatchHalo) -
+                                                                 std::max<int64_t>(0, j0 - kBatchHalo);
             int64_t S = 0;
             double est = 0.0;
             if (uniform_[i]) {
@@ -417,7 +573,7 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
     if (count < 1 || !koff || !qoff) return SOLVE_E_ARG;
     if (count > 0x7fffffffLL) return SOLVE_E_SIZE;
     if (!valid_tuning(t)) return SOLVE_E_ARG;
-    if (precision != SOLVE_FP64) return SOLVE_E_ARG;
+    if (precision != SOLVE_FP64 && precision != SOLVE_FP32_REFINE) return SOLVE_E_ARG;
     if (koff[0] != 0 || qoff[0] != 0) return SOLVE_E_ARG;
     n_.assign(count, 0);
     m_.assign(count, 0);
@@ -448,7 +604,9 @@ int Batch::retile(const spline_tuning& t) {
     tuning_ = t;
     wave_ch_ = wave_ch_for(max_n_);
     make_tables();
-    return ensure(&d_tables_, &cap_tables_, table_bytes());
+    int rc = ensure(&d_tables_, &cap_tables_, table_bytes());
+    if (!rc && !lane_.empty()) rc = ensure(&d_bad_, &cap_bad_, sizeof(int32_t) * (size_t)count_);
+    return rc;
 }
 
 size_t Batch::offset_lane() const { return (witems_.size() * sizeof(WaveItem) + 255) & ~(size_t)255; }
@@ -492,33 +650,28 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     a.n_witems = (int64_t)witems_.size();
     a.lane_curves = (const int32_t*)((const char*)tables + offset_lane());
     a.n_lane = (int64_t)lane_.size();
+    a.prebuilt_max_n = prebuilt_max_n_;
+    a.bad = (int32_t*)d_bad_;
+    const bool mixed = precision_ == SOLVE_FP32_REFINE;
     if (a.n_lane > 0) {
-        const unsigned g = (unsigned)((a.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
-        const int64_t lane_max = lane_max_n_;
-        if (lane_max <= kGroupLanes * 4) group_build_kernel<4><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
-        else if (lane_max <= kGroupLanes * 9) group_build_kernel<9><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
-        else group_build_kernel<16><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
-    }
-    a.prebuilt_max_n = (tuning_.fused == 2) ? kLaneBuildMaxN : 0;
-    int rc = SOLVE_E_ARG;
-    if (tuning_.fused == 2 && max_n_ <= kLaneBuildMaxN) {
-        switch (wave_ch_) {
-            case 1: rc = launch_waves_ch<1, false>(a, tuning_, num_cu_, s); break;
-            case 2: rc = launch_waves_ch<2, false>(a, tuning_, num_cu_, s); break;
-            case 3: rc = launch_waves_ch<3, false>(a, tuning_, num_cu_, s); break;
-            case 4: rc = launch_waves_ch<4, false>(a, tuning_, num_cu_, s); break;
-            default: break;
-        }
-    } else {
-        switch (wave_ch_) {
-            case 1: rc = launch_waves_ch<1, true>(a, tuning_, num_cu_, s); break;
-            case 2: rc = launch_waves_ch<2, true>(a, tuning_, num_cu_, s); break;
-            case 3: rc = launch_waves_ch<3, true>(a, tuning_, num_cu_, s); break;
-            case 4: rc = launch_waves_ch<4, true>(a, tuning_, num_cu_, s); break;
-            case kWaveMaxCH: rc = launch_waves_ch<kWaveMaxCH, true>(a, tuning_, num_cu_, s); break;
-            default: break;
+        if (!a.bad) return SOLVE_E_ARG;
+        if (mixed) {
+            if (lane_max_n_ <= 256) mixed_build_kernel<256><<<(unsigned)a.n_lane, kWave, 0, s>>>(a);
+            else mixed_build_kernel<SOLVE_MAX_N_BATCH><<<(unsigned)a.n_lane, kWave, 0, s>>>(a);
+        } else {
+            const unsigned g = (unsigned)((a.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
+            const int64_t lane_max = lane_max_n_;
+            if (lane_max <= kGroupLanes * 4) group_build_kernel<4><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
+            else if (lane_max <= kGroupLanes * 9) group_build_kernel<9><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
+            else group_build_kernel<16><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(a);
         }
     }
+    // phase 2: the kernel holds the span solve only if some curve needs it
+    const bool build = max_n_ > prebuilt_max_n_;
+    int rc;
+    if (mixed) rc = launch_waves_any<false, true>(wave_ch_, a, tuning_, num_cu_, s);
+    else if (build) rc = launch_waves_any<true, false>(wave_ch_, a, tuning_, num_cu_, s);
+    else rc = launch_waves_any<false, false>(wave_ch_, a, tuning_, num_cu_, s);
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }

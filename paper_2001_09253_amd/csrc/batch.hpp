@@ -58,6 +58,7 @@ struct BatchDevArgs {
     const int32_t* lane_curves;  // curves built in phase 1, longest first
     int64_t n_lane;
     int64_t prebuilt_max_n;      // curves up to this length were built in phase 1 (0: none)
+    int32_t* bad;                // per curve, from phase 1: 1 if its knots are not increasing
 };
 
 // Host side of a batch: the work tables and the device buffers that hold them.
@@ -116,6 +117,9 @@ private:
     std::vector<WaveItem> witems_;
     std::vector<int32_t> lane_;
     int64_t lane_max_n_ = 0;
+    int64_t prebuilt_max_n_ = 0;
+    void* d_bad_ = nullptr;
+    size_t cap_bad_ = 0;
     size_t offset_lane() const;
     void* d_tables_ = nullptr;
     size_t cap_tables_ = 0;

@@ -219,3 +219,62 @@ def test_batch_result_independent_of_company():
         api.spline_plan_run(p1, b1, s1)
         np.testing.assert_array_equal(host(b1["yq"]), all_yq[b.qoff[i]:b.qoff[i + 1]])
         np.testing.assert_array_equal(host(b1["ypp"]), all_ypp[b.koff[i]:b.koff[i + 1]])
+
+
+# Mixed precision (FP32 sweeps, FP64 residual refinement of y'', FP32 cubic
+# term of the evaluation around the FP64 linear part).  Bounds, in the
+# per-instance scaled metric |g - o| / (|o| + max|o|):
+#   y'': two refinement steps take the FP32 solve error (~2^-24 times the
+#        system's conditioning per step) far below 1e-9;
+#   y_q: the FP32 cubic term carries a few 2^-24 of its own size, which can
+#        exceed the values' scale by a small factor: 4e-6 (the 4096-curve
+#        batch measures 1.2e-6 at most, 1.4e-7 at the median).
+MIXED_YPP_TOL = 1e-9
+MIXED_YQ_TOL = 4e-6
+
+
+def mixed_errors(b, yq, ypp, o):
+    from gpu_util import close
+    o_yq, o_ypp, _, _ = o
+    e_yq, e_ypp = [], []
+    for i in range(b.count):
+        k0, k1 = b.koff[i], b.koff[i + 1]
+        q0, q1 = b.qoff[i], b.qoff[i + 1]
+        e_ypp.append(close(ypp[k0:k1], o_ypp[k0:k1])[1])
+        e_yq.append(close(yq[q0:q1], o_yq[q0:q1])[1])
+    return np.array(e_yq), np.array(e_ypp)
+
+
+@pytest.mark.parametrize("tuning", [(256, 4096, 0, 2), (64, 1024, 0, 1)])
+def test_mixed_precision_within_stated_error(small_batch, small_batch_oracle, tuning):
+    b = small_batch
+    plan = api.spline_plan_create(b.koff, b.qoff, precision=api.FP32_REFINE, tuning=api.Tuning(*tuning))
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    assert np.all(host(st) == 0)
+    e_yq, e_ypp = mixed_errors(b, host(bufs["yq"]), host(bufs["ypp"]), small_batch_oracle)
+    assert e_ypp.max() <= MIXED_YPP_TOL, e_ypp.max()
+    assert e_yq.max() <= MIXED_YQ_TOL, e_yq.max()
+    # and it is really the FP32 path: the FP64 path is far closer
+    assert e_yq.max() > 1e-12
+
+
+def test_mixed_precision_long_curves_and_bad_knots():
+    n = np.array([3, 13, 300, 1000, api.MAX_N_BATCH, 130], dtype=np.int64)
+    m = np.array([5, 2048, 40000, 7, 100000, 20480], dtype=np.int64)
+    b = w.batch_from_sizes(29, n, m)
+    x = b.x.copy()
+    x[b.koff[5] + 3] = x[b.koff[5] + 2]  # curve 5: repeated knot
+    b = w.Batch(b.koff, b.qoff, x, b.y, b.sd, b.ed)
+    o = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
+    plan = api.spline_plan_create(b.koff, b.qoff, precision=api.FP32_REFINE)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    s = host(st)
+    assert s[5] == api.E_ORDER and np.all(s[:5] == 0)
+    yq, ypp = host(bufs["yq"]), host(bufs["ypp"])
+    assert np.all(np.isnan(ypp[b.koff[5]:b.koff[6]])) and np.all(np.isnan(yq[b.qoff[5]:b.qoff[6]]))
+    good = w.Batch(b.koff[:6], b.qoff[:6], b.x[:b.koff[5]], b.y[:b.koff[5]], b.sd[:5], b.ed[:5])
+    og = oracle.batch_uniform(good.koff, good.qoff, good.x, good.y, good.sd, good.ed)
+    e_yq, e_ypp = mixed_errors(good, yq[:good.qoff[-1]], ypp[:good.koff[-1]], og)
+    assert e_ypp.max() <= MIXED_YPP_TOL and e_yq.max() <= MIXED_YQ_TOL, (e_ypp, e_yq)
