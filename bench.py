@@ -40,12 +40,8 @@ CSRC = os.path.join(ROOT, "paper_2001_09253_amd", "csrc")
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+    from paper_2001_09253_amd.profiling import kernel_source_hash as ksh
+    return ksh()
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -99,16 +95,19 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     for _ in range(args.warmup):
         api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(K)]
+    # one event pair around the K back-to-back launches on the launch stream:
+    # the average launch duration without per-launch event overhead
+    e_begin = torch.cuda.Event(enable_timing=True)
+    e_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e_begin.record(stream)
     for k in range(K):
-        ev[k][0].record(stream)
         api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
-        ev[k][1].record(stream)
+    e_end.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    solve_ms = e_begin.elapsed_time(e_end) / K
     step_s = (t1 - t0) / K
     value = (n + m) / step_s
     # algorithmic bytes per launch of the fused kernel: read x, y (16 n),
@@ -179,15 +178,16 @@ def bench_batched(args, precision):
         api.spline_plan_replay(plan, stream=stream)
     stream.synchronize()
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(K)]
+    e_begin = torch.cuda.Event(enable_timing=True)
+    e_end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e_begin.record(stream)
     for k in range(K):
-        ev[k][0].record(stream)
         api.spline_plan_replay(plan, stream=stream)
-        ev[k][1].record(stream)
+    e_end.record(stream)
     stream.synchronize()
     t1 = time.perf_counter()
-    launch_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    launch_ms = e_begin.elapsed_time(e_end) / K  # one replay: every launch of the step
     step_s = (t1 - t0) / K
     N, M = int(b.koff[-1]), int(b.qoff[-1])
     value = (N + M) / step_s
@@ -323,13 +323,38 @@ def bench_served(args):
     return out
 
 
+def bench_copy(args):
+    """Calibration only: a plain device-to-device copy of 256 MiB (reads and
+    writes 256 MiB per launch), the reference the HBM traffic counters of the
+    other workloads are scaled by."""
+    import torch
+
+    nbytes = 256 << 20
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    return {"metric": "copy calibration (not a product metric)", "value": 2.0 * nbytes / (ms * 1e-3) / 1e9,
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy: 256 MiB device to device", "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "plain2x", "batched", "mixed", "served"])
+                    choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
@@ -351,6 +376,8 @@ def main():
     elif args.workload in ("batched", "mixed"):
         from paper_2001_09253_amd import api
         out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)
+    elif args.workload == "copy":
+        out = bench_copy(args)
     else:
         out = bench_served(args)
     print(json.dumps(out))
