@@ -187,18 +187,6 @@ struct WaveSmem {
     int32_t bq[kRows + 1];
 };
 
-// The cubic part of newint, (xa^2 - ba^2) xa y''_b + (bx^2 - ba^2) bx y''_a,
-// in FP64, or (MIXED) in FP32 around the FP64 linear part.
-template <bool MIXED>
-__device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, double up, double vp) {
-    if constexpr (MIXED) {
-        const float xf = (float)xa, bf = (float)bx, b2 = (float)ba2;
-        return (double)((xf * xf - b2) * xf * (float)vp + (bf * bf - b2) * bf * (float)up);
-    } else {
-        return (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
-    }
-}
-
 // One wave item.  All 64 lanes of the wavefront call this.  BUILD: items of
 // curves past a.prebuilt_max_n knots solve their span here; curves up to that
 // length were built by phase 1.
@@ -301,121 +289,8 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
     const int64_t k0 = ka + per * it.s + min((int64_t)it.s, rem);
     const int64_t k1 = k0 + per + ((int64_t)it.s < rem ? 1 : 0);
     if (k0 >= k1) return;
-    double* __restrict__ out = a.yq + qo;
-    const double dl = (double)lane;
-    // intervals of the share's first and last query: j0 plus the interior
-    // knots of the block below each
-    int t0, t1;
-    {
-        const double qa = uniform_query(x0, xl, h, m, k0);
-        const double qb = uniform_query(x0, xl, h, m, k1 - 1);
-        int ca = 0, cb = 0;
-        for (int j = j0 + 1 + lane; j - lane < j1; j += kWave) {
-            const double xj = j < j1 ? sm.sx[j - lo] : 0.0;
-            ca += __popcll(__ballot(j < j1 && xj < qa));
-            cb += __popcll(__ballot(j < j1 && xj < qb));
-        }
-        t0 = j0 + ca;
-        t1 = j0 + cb;
-    }
-    const int nt = t1 - t0 + 1;
-    wave_sync();
-
-    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
-        // many queries per interval: interval by interval, its constants in
-        // registers, up to 64 queries of one interval per store.  bq[i] is the
-        // first query of interval t0 + i, less k0.
-        for (int c = lane; c <= nt; c += kWave) {
-            int64_t v;
-            if (c == 0) v = k0;
-            else if (c == nt) v = k1;
-            else v = min(max(first_query_above_r(x0, xl, h, rh, m, sm.sx[t0 + c - lo]), k0), k1);
-            sm.bq[c] = (int32_t)(v - k0);
-        }
-        wave_sync();
-        const double kl0 = (double)k0 + dl;
-        double* __restrict__ o = out + k0 + lane;
-        for (int c = 0; c < nt; ++c) {
-            const int t = t0 + c;
-            const int ks = sm.bq[c];
-            const int ke = sm.bq[c + 1];
-            if (ks >= ke) continue;
-            const double av = sm.sx[t - lo];
-            const double bv = sm.sx[t + 1 - lo];
-            const double u = sm.sy[t - lo];
-            const double v = sm.sy[t + 1 - lo];
-            const double up = sm.so[t - rs];
-            const double vp = sm.so[t + 1 - rs];
-            const double inv = sm.inv[t - j0];
-            const double ba = bv - av;
-            const double ba2 = ba * ba;
-            // kr = k0 + lane + r is the query index k exactly (integers below
-            // 2^53 in double), so x0 + kr*h, one multiply then one add, is the
-            // position uniform_query(.., k) bit for bit (query m-1 aside,
-            // which is x[n-1] itself and is patched below)
-            double kr = kl0 + (double)ks;
-            double* __restrict__ ob = o + ks;
-            int r = ks;
-            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
-                double q0, q1;
-                {
-#pragma clang fp contract(off)
-                    const double s0 = kr * h;
-                    const double s1 = (kr + (double)kWave) * h;
-                    q0 = x0 + s0;
-                    q1 = x0 + s1;
-                }
-                // a6: newint with the interval's 1/(b - a) and (b - a)^2
-                const double xa0 = q0 - av, bx0 = bv - q0;
-                const double xa1 = q1 - av, bx1 = bv - q1;
-                const double l0 = xa0 * v + bx0 * u;
-                const double l1 = xa1 * v + bx1 * u;
-                const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
-                const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
-                ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
-                ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
-                ob += 2 * kWave;
-                kr += (double)(2 * kWave);
-            }
-            for (; r < ke; r += kWave) {
-                double q;
-                {
-#pragma clang fp contract(off)
-                    const double st = kr * h;
-                    q = x0 + st;
-                }
-                const double xa = q - av, bx = bv - q;
-                const double l = xa * v + bx * u;
-                const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
-                if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
-                ob += kWave;
-                kr += (double)kWave;
-            }
-        }
-        if (k1 == m && m > 1 && lane == 0) {
-            // query m-1 is x[n-1] itself (for m > 1), in interval t1
-            const int t = t1;
-            out[m - 1] = newint(xl, sm.sx[t - lo], sm.sx[t + 1 - lo], sm.sy[t - lo], sm.sy[t + 1 - lo],
-                                sm.so[t - rs], sm.so[t + 1 - rs], sm.inv[t - j0]);
-        }
-        return;
-    }
-    // fewer queries per interval: 64 consecutive queries at a time; each lane
-    // finds its own interval from the wavefront's current one (the knots of
-    // the touched intervals are few per chunk)
-    int t = t0;
-    for (int64_t kc = k0; kc < k1; kc += kWave) {
-        const int64_t k = kc + lane;
-        const bool live = k < k1;
-        const double q = uniform_query(x0, xl, h, m, live ? k : k1 - 1);
-        int tl = t;
-        while (tl + 1 <= t1 && sm.sx[tl + 1 - lo] < q) ++tl;
-        t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
-        if (live) {
-            out[k] = newint(q, sm.sx[tl - lo], sm.sx[tl + 1 - lo], sm.sy[tl - lo], sm.sy[tl + 1 - lo],
-                            sm.so[tl - rs], sm.so[tl + 1 - rs], sm.inv[tl - j0]);
-        }
-    }
+    wave_eval_block<MIXED>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, a.yq + qo,
+                           lane);
 }
 
 template <int CH, int WPG, bool BUILD, bool MIXED>

@@ -1,26 +1,27 @@
 // One curve, the whole hot path in one launch (C ABI: spline_solve_uniform).
 //
-// Work is split by knot blocks: block k owns the intervals [k*BK, (k+1)*BK)
-// and every uniform query whose interval lies there.  A workgroup takes a
-// block, solves for y'' on the block's knots by itself -- the paper's
-// tridiagonal rows over the block plus HALO rows on either side, with the
-// coupling to the rows beyond the halo dropped -- and then evaluates the
-// block's queries.  Workgroups never wait on each other.
+// Work is split by knot blocks: a block owns some intervals and every uniform
+// query whose interval lies there.  It solves for y'' on its knots by itself
+// -- the paper's tridiagonal rows over the block plus a halo of rows on either
+// side, with the coupling to the rows beyond the halo dropped -- and then
+// evaluates its queries.  Nothing waits on anything else.
 //
-// Why the halo makes this exact to rounding: the system is strictly
-// diagonally dominant with b_j = 2(a_j + c_j) (section "Generating Second
-// Derivatives").  In Thomas' forward sweep a perturbation of d'_{j-1} reaches
-// d'_j multiplied by a_j / (b_j - a_j c'_{j-1}) < 2/3 (since 0 <= c' <= 1/2),
-// and in the back-substitution a perturbation of y''_{j+1} reaches y''_j
-// multiplied by |c'_j| <= 1/2.  Dropping the coupling HALO rows away
-// therefore changes the block's y'' by at most about 4.5 (2/3)^HALO +
-// (1/2)^HALO times max|y''| -- below 1e-21 max|y''| for HALO = 128, far
-// under FP64 rounding of the values themselves.  Curves shorter than the
-// block plus both halos are solved whole, exactly.
+// Why a halo makes this exact to rounding: the system is strictly diagonally
+// dominant with b_j = 2(a_j + c_j) (section "Generating Second Derivatives").
+// In Thomas' forward sweep a perturbation of d'_{j-1} reaches d'_j multiplied
+// by a_j / (b_j - a_j c'_{j-1}) < 2/3 (since 0 <= c' <= 1/2), and in the back
+// substitution a perturbation of y''_{j+1} reaches y''_j multiplied by
+// |c'_j| <= 1/2.  A uniform halo of 128 rows therefore changes the block's y''
+// by less than 1e-21 max|y''|; the dense kernel below takes each block's
+// halo from the knots themselves (adaptive_halo), shortest that keeps the
+// same kind of bound under 2^-60 max|y''|.  Curves shorter than the block
+// plus both halos are solved whole, exactly.
 //
+// Dense curves (many queries per interval) take one wavefront per block (or
+// per share of a block's queries); sparse curves one workgroup per block.
 // Every y'' is written by the one block that owns it and every query is
-// evaluated by one block (its first and last query are found by an exact
-// search over the query index), so results do not depend on the grid.
+// evaluated once (a block's first and last query are found by an exact search
+// over the query index), so results do not depend on the grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,10 +41,9 @@ struct BlockSolve {
     static constexpr int kChunk = (kSpan + kSolveBlock - 1) / kSolveBlock;  // rows per lane
 };
 
-// DENSE: the block's queries outnumber its intervals several times over, so
-// each wavefront walks (interval, 64 queries) chunks with the interval known
-// for the whole chunk; otherwise each query searches the block's knots.
-template <int BK, bool DENSE>
+// Sparse curves (few queries per interval): every query searches the block's
+// knots.
+template <int BK>
 __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double* __restrict__ x,
                                                                    const double* __restrict__ y, int64_t n,
                                                                    double sd, double ed, int64_t m,
@@ -57,7 +57,6 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
     __shared__ Interval rec[BK];
     __shared__ double kx[BK + 1];
     __shared__ int64_t kq[BK + 1];   // first query of each interval, then the block's end
-    __shared__ int32_t kc[BK + 1];   // exclusive prefix of 64-query chunks per interval
     __shared__ Fwd lds_f[kSolveBlock / kWave];
     __shared__ Bwd lds_b[kSolveBlock / kWave];
     const int tid = threadIdx.x;
@@ -101,25 +100,87 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
             kq[t] = (j == 0) ? 0 : (j == ni - 1) ? m : first_query_above(x0, xl, h, m, sx[j - lo]);
         }
         __syncthreads();
-        if constexpr (DENSE) {
-            block_chunk_prefix<kSolveBlock>(kq, kc, nb, tid);
-            dense_chunks<kSolveBlock / kWave, kModeValue, false>(kq, kc, rec, kx, nb, x0, xl, h, m, j0, yq, tid);
-        } else {
-            const int64_t ka = kq[0];
-            const int64_t kz = kq[nb];
-            const double kda = (double)ka;
-            for (int64_t base = 0; ka + base < kz; base += kSolveBlock) {
-                const int64_t loc = base + tid;
-                const int64_t k = ka + loc;
-                if (k < kz) {
-                    const double q = uniform_query_at(x0, xl, h, m, kda, k, loc);
-                    const int li = (int)lower_bound_idx(kx, 1, nb - 1, q) - 1;
-                    yq[k] = newint_rec(q, rec[li]);
-                }
+        const int64_t ka = kq[0];
+        const int64_t kz = kq[nb];
+        const double kda = (double)ka;
+        for (int64_t base = 0; ka + base < kz; base += kSolveBlock) {
+            const int64_t loc = base + tid;
+            const int64_t k = ka + loc;
+            if (k < kz) {
+                const double q = uniform_query_at(x0, xl, h, m, kda, k, loc);
+                const int li = (int)lower_bound_idx(kx, 1, nb - 1, q) - 1;
+                yq[k] = newint_rec(q, rec[li]);
             }
         }
         __syncthreads();  // the LDS is reused by the next block
     }
+}
+
+// ---------------------------------------------------------------------------
+// Dense curves (many queries per interval): one wavefront per block of BK
+// intervals, no workgroup barriers at all.  The halo is chosen per block from
+// the knots (adaptive_halo: the dropped coupling is bounded below 2^-60 of
+// max|y''| on the block's rows), falling back to the uniform 128 rows; the
+// wavefront solves its span (at most 64 * kWaveSpanCH rows), writes the y''
+// it owns and evaluates the block's queries interval by interval.
+// ---------------------------------------------------------------------------
+constexpr int kWaveSpanCH = 5;           // 320 rows >= kMaxWaveBK + 1 + 2 * kHalo
+constexpr int kMaxWaveBK = 32;
+constexpr int kWavesPerGroup = 4;
+constexpr double kHaloEps = 0x1p-60;
+
+struct WaveSolveSmem {
+    double sx[kWave * kWaveSpanCH + 2];
+    double sy[kWave * kWaveSpanCH + 2];
+    double so[kWave * kWaveSpanCH + 2];
+    double inv[kMaxWaveBK];
+    int32_t bq[kMaxWaveBK + 1];
+};
+
+__global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nblocks, int bk,
+    int shares) {
+    __shared__ WaveSolveSmem smem[kWavesPerGroup];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    WaveSolveSmem& sm = smem[wid];
+    const int n = (int)n64;
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wid;
+    if (item >= nblocks * shares) return;
+    const int64_t blk = item / shares;  // share `sh` of the block's queries (all shares solve the same rows)
+    const int sh = (int)(item - blk * shares);
+    const int j0 = (int)(blk * bk);
+    const int j1 = min(j0 + bk, n - 1);  // intervals [j0, j1)
+    int rs, re;
+    adaptive_halo(x, n, j0, j1, kHaloEps, kHalo, lane, &rs, &re);
+    // a1-a4 over rows [rs, re) (at most 320: the per-row scaling keeps the
+    // scan inside the double range without normalising)
+    const bool bad = build_span<kWave, kWaveSpanCH, true, SoloGroup, false>(
+        x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx, nullptr, nullptr, SoloGroup{}, lane, sm.sy, sm.so);
+    if (bad && status && lane == 0) atomicMin(status, kStatusOrder);
+    const int lo = max(rs - 1, 0);  // knot j staged at [j - lo]; y'' of row i at so[i - rs]
+    if (ypp && sh == 0) {
+        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+        for (int j = j0 + lane; j < jend; j += kWave) ypp[j] = sm.so[j - rs];
+    }
+    for (int t = j0 + lane; t < j1; t += kWave) sm.inv[t - j0] = 1.0 / (sm.sx[t + 1 - lo] - sm.sx[t - lo]);
+    // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the
+    // first block)
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    const double rh = (m > 1) ? 1.0 / h : 0.0;
+    const int64_t ka = (j0 == 0) ? 0 : first_query_above_r(x0, xl, h, rh, m, sm.sx[j0 - lo]);
+    const int64_t kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, sm.sx[j1 - lo]);
+    const int64_t len = kb - ka;
+    const int64_t per = len / shares;
+    const int64_t rem = len % shares;
+    const int64_t k0 = ka + per * sh + min((int64_t)sh, rem);
+    const int64_t k1 = k0 + per + ((int64_t)sh < rem ? 1 : 0);
+    wave_sync();
+    if (k0 >= k1) return;
+    wave_eval_block<false>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, yq, lane);
 }
 
 static int cu_count() {
@@ -139,7 +200,7 @@ static int resident_per_cu() {
     static int cached = 0;
     if (!cached) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_blocks_kernel<BK, (BK <= 16)>, kSolveBlock, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_blocks_kernel<BK>, kSolveBlock, 0) !=
                 hipSuccess || v <= 0)
             v = 1;
         cached = v;
@@ -153,7 +214,7 @@ static int launch_blocks(const double* x, const double* y, int64_t n, double sd,
     const int64_t nblocks = (n - 1 + BK - 1) / BK;
     const int64_t slots = (int64_t)cu_count() * resident_per_cu<BK>();
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblocks, slots));
-    solve_blocks_kernel<BK, (BK <= 16)><<<(unsigned)grid, kSolveBlock, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
+    solve_blocks_kernel<BK><<<(unsigned)grid, kSolveBlock, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
                                                                             nblocks);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
@@ -164,7 +225,20 @@ static int launch_blocks(const double* x, const double* y, int64_t n, double sd,
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
-    if (queries_per_knot * 16 >= 1024.0) return launch_blocks<16>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    if (queries_per_knot >= 48.0) {
+        // about 2048 queries per block of bk intervals; denser blocks are cut
+        // into shares of at most about 2700 queries (each share solves the
+        // block's rows again, so shares are kept large enough to amortise it)
+        const int bk = (int)std::min<double>(kMaxWaveBK, std::max(2.0, std::round(2048.0 / queries_per_knot)));
+        const int64_t nblocks = (n - 1 + bk - 1) / bk;
+        const double per_block = queries_per_knot * bk;
+        const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / 2730.0)));
+        const int64_t groups = (nblocks * shares + kWavesPerGroup - 1) / kWavesPerGroup;
+        if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
+        solve_waves_kernel<<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
+                                                                             nblocks, bk, shares);
+        return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+    }
     if (queries_per_knot * 64 >= 1024.0) return launch_blocks<64>(x, y, n, sd, ed, m, yq, ypp, status, s);
     return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, s);
 }

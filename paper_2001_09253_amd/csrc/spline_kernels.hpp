@@ -380,6 +380,70 @@ __device__ __forceinline__ Bwd group_excl_suffix_bwd(Bwd v, int lane, Bwd* incl_
     }
 }
 
+// Exclusive prefix product (in lane order) of one double per lane over a
+// wavefront, with the DPP pattern of the scans above; lane 0 gets 1.
+__device__ __forceinline__ double wave_excl_prefix_prod(double v) {
+    v *= dpp_f64<kDppRowShr1, 0xf>(1.0, v);
+    v *= dpp_f64<kDppRowShr2, 0xf>(1.0, v);
+    v *= dpp_f64<kDppRowShr4, 0xf>(1.0, v);
+    v *= dpp_f64<kDppRowShr8, 0xf>(1.0, v);
+    v *= dpp_f64<kDppRowBcast15, 0xa>(1.0, v);
+    v *= dpp_f64<kDppRowBcast31, 0xc>(1.0, v);
+    return dpp_f64<kDppWaveShr1, 0xf>(1.0, v);
+}
+
+// Rows to solve around the intervals [j0, j1) of a curve so that the y'' of
+// rows j0 .. j1 equal the whole curve's to far below rounding, from the knots
+// alone.  Solving rows [rs, re) instead of [0, n) drops the coupling a_rs y''
+// to the row before and c_{re-1} y'' to the row after.  In Thomas' sweeps over
+// the truncated rows (the paper's recurrences) every c' stays in [0, 1/2], so
+// the forward sweep carries a perturbation entering at row rs into row k
+// multiplied by a_k / (b_k - a_k c'_{k-1}) <= F_k = a_k / (1.5 a_k + 2 c_k),
+// and the back substitution carries one entering at row re-1 into row k
+// multiplied by c'_k <= G_k = c_k / (1.5 a_k + 2 c_k); the entering sizes are
+// at most max|y''| / 2, and the back substitution adds at most a factor 1.5
+// on the forward side.  So rows j0 .. j1 are off by at most
+//     max|y''| (0.75 prod_{k=rs+1}^{j0} F_k + 0.5 prod_{k=j1}^{re-2} G_k),
+// and the halo on each side is the shortest (at most 63 rows) that takes its
+// product below eps, or the uniform hmax rows where F <= 2/3 and G <= 1/2
+// always suffice (then the wavefront's capacity must hold them).  Every lane
+// calls this and receives the same rs, re.
+__device__ __forceinline__ void adaptive_halo(const double* __restrict__ x, int n, int j0, int j1, double eps,
+                                              int hmax, int lane, int* rs_out, int* re_out) {
+    int rs = 0;
+    if (j0 > 0) {
+        const int k = j0 - lane;
+        double f = 0.0;  // rows at or before the first: nothing to drop
+        if (k >= 1) {
+            const double a = x[k] - x[k - 1];
+            const double c = x[k + 1] - x[k];
+            f = a / (1.5 * a + 2.0 * c);
+        }
+        const double p = wave_excl_prefix_prod(f);
+        const bool ok = (k <= 0) || (0.75 * p <= eps);  // NaN never passes
+        const uint64_t b = __ballot(ok);
+        rs = b ? j0 - (int)(__ffsll((long long)b) - 1) : max(0, j0 - hmax);
+        rs = max(rs, 0);
+    }
+    int re = n;
+    if (j1 < n - 1) {
+        const int k = j1 + lane;
+        double g = 0.0;  // rows at or past the last: nothing to drop
+        if (k <= n - 2) {
+            const double a = x[k] - x[k - 1];
+            const double c = x[k + 1] - x[k];
+            g = c / (1.5 * a + 2.0 * c);
+        }
+        const double q = wave_excl_prefix_prod(g);
+        const bool ok = (k + 1 >= n) || (0.5 * q <= eps);
+        const uint64_t b = __ballot(ok);
+        re = b ? j1 + 1 + (int)(__ffsll((long long)b) - 1) : min(n, j1 + 1 + hmax);
+        re = min(re, n);
+    }
+    *rs_out = rs;
+    *re_out = re;
+}
+
 // Cross-workgroup signalling.  On a multi-XCD device an agent-scope acquire
 // or release maintains the XCD's L2 (write back / invalidate), so a poll loop
 // must not acquire on every iteration: it polls with relaxed atomic loads and
@@ -955,6 +1019,146 @@ __device__ void eval_uniform_range(const double* __restrict__ x, const double* _
         double v = 0.0;
         if constexpr (MODE == kModeValue) v = newint_rec(q, sm.rec[li]);
         put_result<MODE, NT_STORE>(out, k, v, base + li);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One wavefront evaluates the uniform queries k0 .. k1-1 of a curve, all of
+// which lie in the intervals [j0, j1) of a block whose knots j (lo <= j <= j1)
+// are staged at sx[j - lo] and sy[j - lo], whose y'' of row j is at so[j - rs],
+// and whose 1/(x_{t+1} - x_t) of interval t is at sinv[t - j0].  bq: LDS of
+// at least j1 - j0 + 1 int32 for the wavefront's own use.  out is the curve's
+// output array (query k at out[k]).
+// ---------------------------------------------------------------------------
+// The cubic part of newint, (xa^2 - ba^2) xa y''_b + (bx^2 - ba^2) bx y''_a,
+// in FP64, or (MIXED) in FP32 around the FP64 linear part.
+template <bool MIXED>
+__device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, double up, double vp) {
+    if constexpr (MIXED) {
+        const float xf = (float)xa, bf = (float)bx, b2 = (float)ba2;
+        return (double)((xf * xf - b2) * xf * (float)vp + (bf * bf - b2) * bf * (float)up);
+    } else {
+        return (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
+    }
+}
+
+template <bool MIXED>
+__device__ void wave_eval_block(const double* sx, const double* sy, const double* so, const double* sinv,
+                                int32_t* bq, int lo, int rs, int j0, int j1, double x0, double xl, double h,
+                                double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane) {
+    const double dl = (double)lane;
+    // intervals of the range's first and last query: j0 plus the interior
+    // knots of the block below each
+    int t0, t1;
+    {
+        const double qa = uniform_query(x0, xl, h, m, k0);
+        const double qb = uniform_query(x0, xl, h, m, k1 - 1);
+        int ca = 0, cb = 0;
+        for (int j = j0 + 1 + lane; j - lane < j1; j += kWave) {
+            const double xj = j < j1 ? sx[j - lo] : 0.0;
+            ca += __popcll(__ballot(j < j1 && xj < qa));
+            cb += __popcll(__ballot(j < j1 && xj < qb));
+        }
+        t0 = j0 + ca;
+        t1 = j0 + cb;
+    }
+    const int nt = t1 - t0 + 1;
+    wave_sync();
+
+    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
+        // many queries per interval: interval by interval, its constants in
+        // registers, up to 64 queries of one interval per store.  bq[i] is the
+        // first query of interval t0 + i, less k0.
+        for (int c = lane; c <= nt; c += kWave) {
+            int64_t v;
+            if (c == 0) v = k0;
+            else if (c == nt) v = k1;
+            else v = min(max(first_query_above_r(x0, xl, h, rh, m, sx[t0 + c - lo]), k0), k1);
+            bq[c] = (int32_t)(v - k0);
+        }
+        wave_sync();
+        const double kl0 = (double)k0 + dl;
+        double* __restrict__ o = out + k0 + lane;
+        for (int c = 0; c < nt; ++c) {
+            const int t = t0 + c;
+            const int ks = bq[c];
+            const int ke = bq[c + 1];
+            if (ks >= ke) continue;
+            const double av = sx[t - lo];
+            const double bv = sx[t + 1 - lo];
+            const double u = sy[t - lo];
+            const double v = sy[t + 1 - lo];
+            const double up = so[t - rs];
+            const double vp = so[t + 1 - rs];
+            const double inv = sinv[t - j0];
+            const double ba = bv - av;
+            const double ba2 = ba * ba;
+            // kr = k0 + lane + r is the query index k exactly (integers below
+            // 2^53 in double), so x0 + kr*h, one multiply then one add, is the
+            // position uniform_query(.., k) bit for bit (query m-1 aside,
+            // which is x[n-1] itself and is patched below)
+            double kr = kl0 + (double)ks;
+            double* __restrict__ ob = o + ks;
+            int r = ks;
+            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
+                double q0, q1;
+                {
+#pragma clang fp contract(off)
+                    const double s0 = kr * h;
+                    const double s1 = (kr + (double)kWave) * h;
+                    q0 = x0 + s0;
+                    q1 = x0 + s1;
+                }
+                // a6: newint with the interval's 1/(b - a) and (b - a)^2
+                const double xa0 = q0 - av, bx0 = bv - q0;
+                const double xa1 = q1 - av, bx1 = bv - q1;
+                const double l0 = xa0 * v + bx0 * u;
+                const double l1 = xa1 * v + bx1 * u;
+                const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
+                const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
+                ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
+                ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                ob += 2 * kWave;
+                kr += (double)(2 * kWave);
+            }
+            for (; r < ke; r += kWave) {
+                double q;
+                {
+#pragma clang fp contract(off)
+                    const double st = kr * h;
+                    q = x0 + st;
+                }
+                const double xa = q - av, bx = bv - q;
+                const double l = xa * v + bx * u;
+                const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
+                if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
+                ob += kWave;
+                kr += (double)kWave;
+            }
+        }
+        if (k1 == m && m > 1 && lane == 0) {
+            // query m-1 is x[n-1] itself (for m > 1), in interval t1
+            const int t = t1;
+            out[m - 1] = newint(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
+                                so[t - rs], so[t + 1 - rs], sinv[t - j0]);
+        }
+        return;
+    }
+    // fewer queries per interval: 64 consecutive queries at a time; each lane
+    // finds its own interval from the wavefront's current one (the knots of
+    // the touched intervals are few per chunk)
+    int t = t0;
+    for (int64_t kc = k0; kc < k1; kc += kWave) {
+        const int64_t k = kc + lane;
+        const bool live = k < k1;
+        const double q = uniform_query(x0, xl, h, m, live ? k : k1 - 1);
+        int tl = t;
+        while (tl + 1 <= t1 && sx[tl + 1 - lo] < q) ++tl;
+        t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
+        if (live) {
+            out[k] = newint(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
+                            so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
+        }
     }
 }
 

@@ -67,6 +67,30 @@ def alternating_curve(rng: np.random.Generator, n: int, small: float = 1e-3, sca
     return x, y
 
 
+def spacing_curve(rng: np.random.Generator, n: int, kind: str):
+    """Knots with adversarial spacing and standard-normal values, x_0 = 0:
+      "sawtooth_down": runs of widths 1, 0.1, ..., 1e-7 (each much narrower
+          than the one before it);
+      "sawtooth_up":   runs of widths 1e-7, ..., 0.1, 1;
+      "loguniform":    widths log-uniform over 12 orders of magnitude;
+      "clustered":     U(0,1) widths with every 97th width shrunk by 1e-6."""
+    k = np.arange(n - 1)
+    if kind == "sawtooth_down":
+        w = 10.0 ** (-(k % 8).astype(np.float64))
+    elif kind == "sawtooth_up":
+        w = 10.0 ** ((k % 8).astype(np.float64) - 7.0)
+    elif kind == "loguniform":
+        w = 10.0 ** rng.uniform(-12.0, 0.0, n - 1)
+    elif kind == "clustered":
+        w = rng.random(n - 1)
+        w[::97] *= 1e-6
+        w[w == 0] = 1.0
+    else:
+        raise ValueError(kind)
+    x = np.concatenate([[0.0], np.cumsum(w)])
+    return x, rng.standard_normal(n)
+
+
 def bc_for(i: int):
     """(name, start_deriv, end_deriv) of the i-th instance in the cycle."""
     return BC_CASES[i % len(BC_CASES)]

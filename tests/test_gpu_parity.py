@@ -242,6 +242,27 @@ def test_solve_uniform_halo_worst_case_decay():
         assert_close(host(yq), o_yq, "decay yq")
 
 
+@pytest.mark.parametrize("kind", ["sawtooth_down", "sawtooth_up", "loguniform", "clustered"])
+@pytest.mark.parametrize("bc", [0, 3])
+def test_solve_uniform_adaptive_halo_adversarial_spacing(kind, bc):
+    # Dense queries take the kernel that sizes each block's halo from the
+    # knots; these spacings keep the per-row decay factors near their bounds
+    # in long runs.
+    name, sd, ed = BCS[bc]
+    n = 4000
+    x, y = w.spacing_curve(np.random.default_rng(31 + bc), n, kind)
+    for m in (n * 60, n * 400):
+        xd, yd = dev(x), dev(y)
+        ypp = torch.full_like(xd, np.nan)
+        yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
+        st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        api.spline_solve_uniform(xd, yd, sd, ed, m, yq, ypp, st)
+        o_yq, o_ypp = oracle.spline_uniform(x, y, sd, ed, m)
+        assert int(host(st)[0]) == api.OK
+        assert_close(host(ypp), o_ypp, "%s ypp m=%d %s" % (kind, m, name))
+        assert_close(host(yq), o_yq, "%s yq m=%d %s" % (kind, m, name))
+
+
 def test_solve_uniform_bad_knots_and_reuse():
     x, y = w.paper_curve(np.random.default_rng(21), 9000)
     xb = x.copy()
