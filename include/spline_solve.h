@@ -106,9 +106,11 @@ int solve_create(const solve_config *cfg, solve_ctx **out);
  * detected per pointer); they are copied before the call returns, so the
  * caller may free them at once.  start_deriv/end_deriv: see the conventions.
  * xq: m explicit query points, or NULL for m uniform queries.  yq_out: m
- * results, ypp_out: n second derivatives or NULL; both caller-owned, host or
- * device, and written only when the request completes -- they must stay valid
- * until solve_poll reports DONE/ERROR or until solve_destroy.  *ticket_out
+ * results, ypp_out: n second derivatives or NULL; both caller-owned, device,
+ * pinned host (written by the device directly) or pageable host (copied from
+ * the library's pinned staging), and written only when the request completes
+ * -- they must stay valid until solve_poll reports DONE/ERROR or until
+ * solve_destroy.  *ticket_out
  * receives the request's ticket.  Errors: E_ARG, E_SIZE (n < 3, m < 1,
  * n > SOLVE_MAX_N_BATCH without SOLVE_PLAIN, n > SOLVE_MAX_N_BLOCK), E_ORDER
  * (the copied knots are checked before the call returns), E_BUDGET (the

@@ -105,15 +105,23 @@ int hip_fail(const char* what, hipError_t e) {
     return SOLVE_E_DEVICE;
 }
 
-bool is_device_ptr(const void* p) {
-    if (!p) return false;
+// Where a caller's pointer lives: device memory (or managed), pinned host
+// memory (the device copies to and from it directly), or pageable host memory.
+enum class Mem { kDevice, kPinned, kPageable };
+
+Mem mem_kind(const void* p) {
+    if (!p) return Mem::kPageable;
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) {
         (void)hipGetLastError();  // clear the sticky error of an unknown host pointer
-        return false;
+        return Mem::kPageable;
     }
-    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return Mem::kDevice;
+    if (a.type == hipMemoryTypeHost) return Mem::kPinned;
+    return Mem::kPageable;
 }
+
+bool is_device_ptr(const void* p) { return mem_kind(p) == Mem::kDevice; }
 
 struct Req {
     solve_ticket id = 0;
@@ -123,6 +131,7 @@ struct Req {
     double* yq_out = nullptr;
     double* ypp_out = nullptr;
     bool yq_dev = false, ypp_dev = false;
+    bool yq_pinned = false, ypp_pinned = false;  // the device writes these directly
     int status = SOLVE_PENDING;
     int code = SOLVE_OK;
     double t[4] = {0, 0, 0, 0};
@@ -175,6 +184,8 @@ struct Slot {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+constexpr uint64_t kSpinPolls = 20000;  // about a few ms of yields before the scheduler sleeps between polls
+
 constexpr int32_t kStatusUnset = 0x7fffffff;
 
 }  // namespace
@@ -191,6 +202,7 @@ struct solve_ctx {
     bool stop = false;
     bool inject = false;
     bool failed_state = false;
+    uint64_t spins = 0;  // scheduler polls since a batch last completed
     uint64_t next_ticket = 1;
     uint64_t resident = 0, peak_resident = 0, resident_reqs = 0;
     uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_batches = 0, peak_batch = 0;
@@ -244,8 +256,8 @@ int launch_batch(solve_ctx* c, Slot& s) {
             xt += r.m;
             s.uniform[i] = 0;
         }
-        host_yq |= !r.yq_dev;
-        host_ypp |= r.ypp_out && !r.ypp_dev;
+        host_yq |= !r.yq_dev && !r.yq_pinned;
+        host_ypp |= r.ypp_out && !r.ypp_dev && !r.ypp_pinned;
     }
     nt = s.koff[count];
     mt = s.qoff[count];
@@ -316,10 +328,13 @@ int launch_batch(solve_ctx* c, Slot& s) {
     // callers are served from one copy of the output region.
     for (int64_t i = 0; i < count && !rc; ++i) {
         const Req& r = *s.reqs[i];
-        if (r.yq_dev && hipMemcpyAsync(r.yq_out, dyq + s.qoff[i], 8 * r.m, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        if ((r.yq_dev || r.yq_pinned) &&
+            hipMemcpyAsync(r.yq_out, dyq + s.qoff[i], 8 * r.m,
+                           r.yq_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = SOLVE_E_DEVICE;
-        if (!rc && r.ypp_out && r.ypp_dev &&
-            hipMemcpyAsync(r.ypp_out, dypp + s.koff[i], 8 * r.n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        if (!rc && r.ypp_out && (r.ypp_dev || r.ypp_pinned) &&
+            hipMemcpyAsync(r.ypp_out, dypp + s.koff[i], 8 * r.n,
+                           r.ypp_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = SOLVE_E_DEVICE;
     }
     const size_t back = host_ypp ? s.out_bytes : host_yq ? s.o_ypp : s.o_yq;
@@ -348,8 +363,9 @@ void deliver(Slot& s) {
         Req& r = *s.reqs[i];
         if (s.failed) continue;
         r.code = s.hout_at<int32_t>(s.o_status)[i];
-        if (!r.yq_dev) std::memcpy(r.yq_out, s.hout_at<double>(s.o_yq) + s.qoff[i], 8 * r.m);
-        if (r.ypp_out && !r.ypp_dev) std::memcpy(r.ypp_out, s.hout_at<double>(s.o_ypp) + s.koff[i], 8 * r.n);
+        if (!r.yq_dev && !r.yq_pinned) std::memcpy(r.yq_out, s.hout_at<double>(s.o_yq) + s.qoff[i], 8 * r.m);
+        if (r.ypp_out && !r.ypp_dev && !r.ypp_pinned)
+            std::memcpy(r.ypp_out, s.hout_at<double>(s.o_ypp) + s.koff[i], 8 * r.n);
     }
 }
 
@@ -412,6 +428,7 @@ void scheduler(solve_ctx* c) {
             s.bytes = 0;
             s.busy = false;
             s.failed = false;
+            c->spins = 0;
             c->cv_done.notify_all();
         }
         // 2. cancel queued work on shutdown
@@ -471,8 +488,21 @@ void scheduler(solve_ctx* c) {
             }
         }
         if (c->stop && c->queue.empty() && !any_busy) break;
-        if (any_busy) c->cv_sched.wait_for(lk, std::chrono::microseconds(20));
-        else c->cv_sched.wait(lk);
+        if (any_busy) {
+            // a batch is on the device: poll its event again at once (the
+            // latency of a finished batch is what a waiting caller sees),
+            // backing off to short sleeps only after a long wait
+            if (++c->spins < kSpinPolls) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                c->cv_sched.wait_for(lk, std::chrono::microseconds(50));
+            }
+        } else {
+            c->spins = 0;
+            c->cv_sched.wait(lk);
+        }
     }
 }
 
@@ -600,8 +630,12 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
     r->ed = end_deriv;
     r->yq_out = yq_out;
     r->ypp_out = ypp_out;
-    r->yq_dev = is_device_ptr(yq_out);
-    r->ypp_dev = ypp_out && is_device_ptr(ypp_out);
+    const Mem kq = mem_kind(yq_out);
+    const Mem kp = ypp_out ? mem_kind(ypp_out) : Mem::kPageable;
+    r->yq_dev = kq == Mem::kDevice;
+    r->yq_pinned = kq == Mem::kPinned;
+    r->ypp_dev = ypp_out && kp == Mem::kDevice;
+    r->ypp_pinned = ypp_out && kp == Mem::kPinned;
     int rc = copy_in(c, r->x, knots, n);
     if (!rc) rc = copy_in(c, r->y, values, n);
     if (!rc && xq) rc = copy_in(c, r->xq, xq, m);

@@ -80,13 +80,18 @@ def _sleep_until(clock, target):
 
 def replay(trace: workloads.Trace, reqs: list[Request], *, plain: bool = False, budget: int = 200 << 30,
            max_slots: int = 65536, max_inflight: int = 2, flags: int = 0, warmup_s: float = 0.0,
-           pool: int = 512, keep_outputs: bool = False, device: int = 0):
+           pool: int = 512, keep_outputs: bool = False, device: int = 0, pinned: bool = True):
     """Run the trace; returns (ReplayResult, outputs or None).  outputs[r] is
-    request r's result copy when keep_outputs."""
+    request r's result copy when keep_outputs.  pinned: the result buffers are
+    pinned host memory (the device writes them directly), else pageable."""
     count = len(reqs)
     mmax = max((q.m for q in reqs), default=1)
     pool = max(1, min(pool, count))
-    bufs = [np.empty(mmax, dtype=np.float64) for _ in range(pool)]
+    if pinned:
+        import torch
+        bufs = [torch.empty(mmax, dtype=torch.float64, pin_memory=True).numpy() for _ in range(pool)]
+    else:
+        bufs = [np.empty(mmax, dtype=np.float64) for _ in range(pool)]
     ctx = api.solve_create(device=device, hbm_budget_bytes=budget, max_slots=max_slots,
                            flags=flags | (api.PLAIN if plain else 0), max_inflight=max_inflight)
     tickets = [None] * count

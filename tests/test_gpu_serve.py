@@ -97,6 +97,27 @@ def test_device_outputs_and_device_inputs():
         assert_close(yq, o_yq, "request %d yq" % r)
 
 
+def test_pinned_host_outputs():
+    reqs = make_reqs(13, SIZES, explicit={2})
+    ctx = api.solve_create()
+    try:
+        outs, tickets = [], []
+        for x, y, sd, ed, xq, m in reqs:
+            yq = torch.full((m,), np.nan, dtype=torch.float64, pin_memory=True)
+            ypp = torch.full((len(x),), np.nan, dtype=torch.float64, pin_memory=True)
+            tickets.append(api.solve_submit(ctx, x, y, sd, ed, xq, m, yq, ypp))
+            outs.append((yq, ypp))
+        for t in tickets:
+            api.solve_wait(ctx, t)
+            assert api.solve_poll(ctx, t) == api.DONE
+    finally:
+        api.solve_destroy(ctx)
+    for r, (req, (yq, ypp)) in enumerate(zip(reqs, outs)):
+        o_yq, o_ypp = expected(req)
+        assert_close(ypp.numpy(), o_ypp, "pinned ypp %d" % r)
+        assert_close(yq.numpy(), o_yq, "pinned yq %d" % r)
+
+
 def test_result_same_alone_and_in_the_mix():
     reqs = make_reqs(3, SIZES, explicit={6})
     ctx = api.solve_create(max_inflight=1)
