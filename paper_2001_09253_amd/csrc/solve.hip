@@ -155,9 +155,16 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     int rs, re;
     adaptive_halo(x, n, j0, j1, kHaloEps, kHalo, lane, &rs, &re);
     // a1-a4 over rows [rs, re) (at most 320: the per-row scaling keeps the
-    // scan inside the double range without normalising)
-    const bool bad = build_span<kWave, kWaveSpanCH, true, SoloGroup, false>(
-        x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx, nullptr, nullptr, SoloGroup{}, lane, sm.sy, sm.so);
+    // scan inside the double range without normalising); the short spans the
+    // adaptive halo gives take a build compiled for 2 rows per lane
+    bool bad;
+    if (re - rs <= kWave * 2)
+        bad = build_span<kWave, 2, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx, nullptr,
+                                                            nullptr, SoloGroup{}, lane, sm.sy, sm.so);
+    else
+        bad = build_span<kWave, kWaveSpanCH, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx,
+                                                                      nullptr, nullptr, SoloGroup{}, lane, sm.sy,
+                                                                      sm.so);
     if (bad && status && lane == 0) atomicMin(status, kStatusOrder);
     const int lo = max(rs - 1, 0);  // knot j staged at [j - lo]; y'' of row i at so[i - rs]
     if (ypp && sh == 0) {
@@ -180,7 +187,10 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     const int64_t k1 = k0 + per + ((int64_t)sh < rem ? 1 : 0);
     wave_sync();
     if (k0 >= k1) return;
-    wave_eval_block<false>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, yq, lane);
+    // (few wavefronts per SIMD here: the next interval's constants are read
+    // while the current one is evaluated)
+    wave_eval_block<false, true>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, yq,
+                                 lane);
 }
 
 static int cu_count() {

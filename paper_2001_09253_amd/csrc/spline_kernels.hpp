@@ -1042,7 +1042,7 @@ __device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, d
     }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool PREFETCH = false>
 __device__ void wave_eval_block(const double* sx, const double* sy, const double* so, const double* sinv,
                                 int32_t* bq, int lo, int rs, int j0, int j1, double x0, double xl, double h,
                                 double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane) {
@@ -1079,62 +1079,92 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         wave_sync();
         const double kl0 = (double)k0 + dl;
         double* __restrict__ o = out + k0 + lane;
+        // interval c's constants (and, with PREFETCH, interval c+1's read
+        // from LDS while interval c is evaluated)
+        int ke = bq[0];
+        int kn = bq[1];
+        double av = sx[t0 - lo], bv = sx[t0 + 1 - lo];
+        double u = sy[t0 - lo], v = sy[t0 + 1 - lo];
+        double up = so[t0 - rs], vp = so[t0 + 1 - rs];
+        double inv = sinv[t0 - j0];
         for (int c = 0; c < nt; ++c) {
-            const int t = t0 + c;
-            const int ks = bq[c];
-            const int ke = bq[c + 1];
-            if (ks >= ke) continue;
-            const double av = sx[t - lo];
-            const double bv = sx[t + 1 - lo];
-            const double u = sy[t - lo];
-            const double v = sy[t + 1 - lo];
-            const double up = so[t - rs];
-            const double vp = so[t + 1 - rs];
-            const double inv = sinv[t - j0];
-            const double ba = bv - av;
-            const double ba2 = ba * ba;
-            // kr = k0 + lane + r is the query index k exactly (integers below
-            // 2^53 in double), so x0 + kr*h, one multiply then one add, is the
-            // position uniform_query(.., k) bit for bit (query m-1 aside,
-            // which is x[n-1] itself and is patched below)
-            double kr = kl0 + (double)ks;
-            double* __restrict__ ob = o + ks;
-            int r = ks;
-            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
-                double q0, q1;
-                {
-#pragma clang fp contract(off)
-                    const double s0 = kr * h;
-                    const double s1 = (kr + (double)kWave) * h;
-                    q0 = x0 + s0;
-                    q1 = x0 + s1;
-                }
-                // a6: newint with the interval's 1/(b - a) and (b - a)^2
-                const double xa0 = q0 - av, bx0 = bv - q0;
-                const double xa1 = q1 - av, bx1 = bv - q1;
-                const double l0 = xa0 * v + bx0 * u;
-                const double l1 = xa1 * v + bx1 * u;
-                const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
-                const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
-                ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
-                ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
-                ob += 2 * kWave;
-                kr += (double)(2 * kWave);
+            const int ks = ke;
+            ke = kn;
+            double av_n = 0.0, bv_n = 0.0, u_n = 0.0, v_n = 0.0, up_n = 0.0, vp_n = 0.0, inv_n = 0.0;
+            const int tn = min(t0 + c + 1, t1);
+            if constexpr (PREFETCH) {
+                kn = bq[min(c + 2, nt)];
+                av_n = sx[tn - lo];
+                bv_n = sx[tn + 1 - lo];
+                u_n = sy[tn - lo];
+                v_n = sy[tn + 1 - lo];
+                up_n = so[tn - rs];
+                vp_n = so[tn + 1 - rs];
+                inv_n = sinv[tn - j0];
             }
-            for (; r < ke; r += kWave) {
-                double q;
-                {
+            if (ks < ke) {
+                const double ba = bv - av;
+                const double ba2 = ba * ba;
+                // kr = k0 + lane + r is the query index k exactly (integers
+                // below 2^53 in double), so x0 + kr*h, one multiply then one
+                // add, is the position uniform_query(.., k) bit for bit (query
+                // m-1 aside, which is x[n-1] itself and is patched below)
+                double kr = kl0 + (double)ks;
+                double* __restrict__ ob = o + ks;
+                int r = ks;
+                for (; r + 2 * kWave <= ke; r += 2 * kWave) {
+                    double q0, q1;
+                    {
 #pragma clang fp contract(off)
-                    const double st = kr * h;
-                    q = x0 + st;
+                        const double s0 = kr * h;
+                        const double s1 = (kr + (double)kWave) * h;
+                        q0 = x0 + s0;
+                        q1 = x0 + s1;
+                    }
+                    // a6: newint with the interval's 1/(b - a) and (b - a)^2
+                    const double xa0 = q0 - av, bx0 = bv - q0;
+                    const double xa1 = q1 - av, bx1 = bv - q1;
+                    const double l0 = xa0 * v + bx0 * u;
+                    const double l1 = xa1 * v + bx1 * u;
+                    const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
+                    const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
+                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
+                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                    ob += 2 * kWave;
+                    kr += (double)(2 * kWave);
                 }
-                const double xa = q - av, bx = bv - q;
-                const double l = xa * v + bx * u;
-                const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
-                if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
-                ob += kWave;
-                kr += (double)kWave;
+                for (; r < ke; r += kWave) {
+                    double q;
+                    {
+#pragma clang fp contract(off)
+                        const double st = kr * h;
+                        q = x0 + st;
+                    }
+                    const double xa = q - av, bx = bv - q;
+                    const double l = xa * v + bx * u;
+                    const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
+                    if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
+                    ob += kWave;
+                    kr += (double)kWave;
+                }
             }
+            if constexpr (!PREFETCH) {
+                kn = bq[min(c + 2, nt)];
+                av_n = sx[tn - lo];
+                bv_n = sx[tn + 1 - lo];
+                u_n = sy[tn - lo];
+                v_n = sy[tn + 1 - lo];
+                up_n = so[tn - rs];
+                vp_n = so[tn + 1 - rs];
+                inv_n = sinv[tn - j0];
+            }
+            av = av_n;
+            bv = bv_n;
+            u = u_n;
+            v = v_n;
+            up = up_n;
+            vp = vp_n;
+            inv = inv_n;
         }
         if (k1 == m && m > 1 && lane == 0) {
             // query m-1 is x[n-1] itself (for m > 1), in interval t1
