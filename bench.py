@@ -91,9 +91,19 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     torch.cuda.synchronize()
     build_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / K
     eval_ms = sum(e[1].elapsed_time(e[2]) for e in ev2) / K
-    # the timed path: one launch per step (build and evaluate fused)
+    # the timed path: one launch per step (build and evaluate fused); with
+    # --variant, the one-launch kernel with one of the paper's evaluation
+    # formulas
+    if args.variant is None:
+        def solve():
+            api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
+    else:
+        code = api.VARIANTS[args.variant]
+
+        def solve():
+            api.spline_solve_uniform_variant(x, y, sd, ed, m, code, yq, ypp)
     for _ in range(args.warmup):
-        api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
+        solve()
     torch.cuda.synchronize()
     # one event pair around the K back-to-back launches on the launch stream:
     # the average launch duration without per-launch event overhead
@@ -103,7 +113,7 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     t0 = time.perf_counter()
     e_begin.record(stream)
     for k in range(K):
-        api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
+        solve()
     e_end.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -113,7 +123,7 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     # algorithmic bytes per launch of the fused kernel: read x, y (16 n),
     # write y'' (8 n) and write the m results (8 m); the halo rows each
     # workgroup re-reads and the y'' it keeps on chip are not counted
-    dom = "solve_uniform"
+    dom = "solve_uniform" if args.variant is None else "solve_uniform[%s]" % args.variant
     dms = solve_ms
     dbytes = 24.0 * n + 8.0 * m
     achieved = dbytes / (dms * 1e-3) / 1e9
@@ -122,11 +132,12 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
         "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload_name, "instances": 1, "n": n, "m": m, "ends": "natural",
+                   "eval_formula": args.variant or "newint (hoisted 1/(b-a))",
                    "seed": 0, "generator": "x_j = x_{j-1} + U(0,1) (0 -> 1e-4), y_j = U(0,1)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, workload_name),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": dms},
-        "kernels_ms": {"solve_uniform": solve_ms, "two_launch_build": build_ms, "two_launch_eval_uniform": eval_ms},
+        "kernels_ms": {dom: solve_ms, "two_launch_build": build_ms, "two_launch_eval_uniform": eval_ms},
         "points_per_s": m / step_s, "knots_per_s": n / step_s,
         "path_gbs": (24.0 * n + 8.0 * m) / step_s / 1e9,
     }
@@ -355,6 +366,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy"])
+    ap.add_argument("--variant", default=None,
+                    choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul"],
+                    help="single-curve workloads: time this evaluation formula on the one-launch kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")

@@ -191,6 +191,27 @@ int spline_solve_uniform(const double *x, const double *y, int64_t n, double sta
                          double end_deriv, int64_t m, double *yq, double *ypp, int32_t *status,
                          void *stream);
 
+/* The per-query formulas compared in the paper's "Benchmarks" section
+ * ("Curve Interpolation": newint, newint__orig, newint__noinv, splint_one__div,
+ * splint_one__mul), for spline_solve_uniform_variant. */
+#define SOLVE_NEWINT_HOISTED 0 /* newint, 1/(b-a) and (b-a)^2 once per interval */
+#define SOLVE_NEWINT_ORIG 1    /* newint with inv_ba = 1/(b-a) formed per query  */
+#define SOLVE_NEWINT_NOINV 2   /* newint dividing by (b-a) per query              */
+#define SOLVE_SPLINT_DIV 3     /* the A,B,C,D form ("Fast Interpolation"), /6     */
+#define SOLVE_SPLINT_MUL 4     /* the same with the /6 as a multiplication        */
+
+/* spline_solve_uniform with the evaluation formula chosen by `variant` (one of
+ * the SOLVE_NEWINT_* / SOLVE_SPLINT_* values), for comparing the paper's
+ * variants on the same build (a1-a5 unchanged).  It always takes the
+ * wavefront-per-knot-block kernel, whatever the query density.  Arguments,
+ * layout, ownership and status as for spline_solve_uniform.  The variants
+ * agree to rounding (a few ulp of max|y| at the query); SOLVE_NEWINT_HOISTED
+ * matches spline_solve_uniform's dense path bit for bit.  Errors: E_ARG (null
+ * pointer, unknown variant), E_SIZE as spline_solve_uniform. */
+int spline_solve_uniform_variant(const double *x, const double *y, int64_t n, double start_deriv,
+                                 double end_deriv, int64_t m, int32_t variant, double *yq, double *ypp,
+                                 int32_t *status, void *stream);
+
 /* Step a5 alone: the interval index of each of the m uniform queries
  * (int32, device, output), computed by the same code as spline_eval_uniform. */
 int spline_bracket_uniform(const double *x, int64_t n, int64_t m, int32_t *idx, void *stream);

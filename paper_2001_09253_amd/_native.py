@@ -47,6 +47,7 @@ SIGNATURES = {
     "solve_destroy": (C.c_int, [_vp]),
     "spline_build": (C.c_int, [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp]),
     "spline_solve_uniform": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _vp, _vp, _vp, _vp]),
+    "spline_solve_uniform_variant": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _i32, _vp, _vp, _vp, _vp]),
     "spline_eval_uniform": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
     "spline_bracket_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),
     "spline_noop_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),

@@ -101,6 +101,28 @@ def spline_solve_uniform(x, y, start_deriv, end_deriv, m, yq, ypp=None, status=N
            "spline_solve_uniform")
 
 
+# evaluation formulas of spline_solve_uniform_variant (the paper's
+# "Curve Interpolation" benchmark variants)
+NEWINT_HOISTED = 0
+NEWINT_ORIG = 1
+NEWINT_NOINV = 2
+SPLINT_DIV = 3
+SPLINT_MUL = 4
+VARIANTS = {"newint": NEWINT_HOISTED, "newint__orig": NEWINT_ORIG, "newint__noinv": NEWINT_NOINV,
+            "splint_one__div": SPLINT_DIV, "splint_one__mul": SPLINT_MUL}
+
+
+def spline_solve_uniform_variant(x, y, start_deriv, end_deriv, m, variant, yq, ypp=None, status=None, stream=None):
+    """spline_solve_uniform on the wavefront-per-block kernel with the
+    evaluation formula `variant` (a VARIANTS value)."""
+    n = x.numel()
+    _check(_native.lib().spline_solve_uniform_variant(
+        _dev(x, name="x"), _dev(y, name="y", numel=n), n, float(start_deriv), float(end_deriv), int(m),
+        int(variant), _dev(yq, name="yq", numel=int(m)), _dev(ypp, name="ypp", numel=n, optional=True),
+        _dev(status, torch.int32, "status", 1, optional=True), _stream(stream)),
+        "spline_solve_uniform_variant")
+
+
 def spline_eval_uniform(x, y, ypp, m, yq, stream=None):
     n = x.numel()
     _check(_native.lib().spline_eval_uniform(_dev(x, name="x"), _dev(y, name="y", numel=n),

@@ -137,6 +137,7 @@ struct WaveSolveSmem {
     int32_t bq[kMaxWaveBK + 1];
 };
 
+template <int VARIANT>
 __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
     double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nblocks, int bk,
@@ -189,8 +190,8 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     if (k0 >= k1) return;
     // (few wavefronts per SIMD here: the next interval's constants are read
     // while the current one is evaluated)
-    wave_eval_block<false, true>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, yq,
-                                 lane);
+    wave_eval_block<false, true, VARIANT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0,
+                                          k1, yq, lane);
 }
 
 static int cu_count() {
@@ -232,23 +233,28 @@ static int launch_blocks(const double* x, const double* y, int64_t n, double sd,
 // Block size from the query density: small blocks when a block's queries
 // alone keep a workgroup busy, larger ones when queries are sparse and the
 // halo rows would dominate.
+template <int VARIANT>
+static int launch_waves_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
+                              double* yq, double* ypp, int32_t* status, hipStream_t s) {
+    const double queries_per_knot = (double)m / (double)(n - 1);
+    // about 2048 queries per block of bk intervals; denser blocks are cut
+    // into shares of at most about 2700 queries (each share solves the
+    // block's rows again, so shares are kept large enough to amortise it)
+    const int bk = (int)std::min<double>(kMaxWaveBK, std::max(2.0, std::round(2048.0 / queries_per_knot)));
+    const int64_t nblocks = (n - 1 + bk - 1) / bk;
+    const double per_block = queries_per_knot * bk;
+    const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / 2730.0)));
+    const int64_t groups = (nblocks * shares + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
+    solve_waves_kernel<VARIANT><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
+                                                                                  status, nblocks, bk, shares);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
-    if (queries_per_knot >= 48.0) {
-        // about 2048 queries per block of bk intervals; denser blocks are cut
-        // into shares of at most about 2700 queries (each share solves the
-        // block's rows again, so shares are kept large enough to amortise it)
-        const int bk = (int)std::min<double>(kMaxWaveBK, std::max(2.0, std::round(2048.0 / queries_per_knot)));
-        const int64_t nblocks = (n - 1 + bk - 1) / bk;
-        const double per_block = queries_per_knot * bk;
-        const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / 2730.0)));
-        const int64_t groups = (nblocks * shares + kWavesPerGroup - 1) / kWavesPerGroup;
-        if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
-        solve_waves_kernel<<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
-                                                                             nblocks, bk, shares);
-        return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
-    }
+    if (queries_per_knot >= 48.0) return launch_waves_solve<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
     if (queries_per_knot * 64 >= 1024.0) return launch_blocks<64>(x, y, n, sd, ed, m, yq, ypp, status, s);
     return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, s);
 }
@@ -263,4 +269,26 @@ extern "C" int spline_solve_uniform(const double* x, const double* y, int64_t n,
     if (!x || !y || !yq) return SOLVE_E_ARG;
     if (n < 3 || n > SOLVE_MAX_N_SOLVE || m < 1) return SOLVE_E_SIZE;
     return launch_solve_uniform(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, (hipStream_t)stream);
+}
+
+extern "C" int spline_solve_uniform_variant(const double* x, const double* y, int64_t n, double start_deriv,
+                                            double end_deriv, int64_t m, int32_t variant, double* yq, double* ypp,
+                                            int32_t* status, void* stream) {
+    if (!x || !y || !yq) return SOLVE_E_ARG;
+    if (n < 3 || n > SOLVE_MAX_N_SOLVE || m < 1) return SOLVE_E_SIZE;
+    hipStream_t s = (hipStream_t)stream;
+    switch (variant) {
+        case SOLVE_NEWINT_HOISTED:
+            return launch_waves_solve<kHoisted>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        case SOLVE_NEWINT_ORIG:
+            return launch_waves_solve<kOrig>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        case SOLVE_NEWINT_NOINV:
+            return launch_waves_solve<kNoinv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        case SOLVE_SPLINT_DIV:
+            return launch_waves_solve<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        case SOLVE_SPLINT_MUL:
+            return launch_waves_solve<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        default:
+            return SOLVE_E_ARG;
+    }
 }

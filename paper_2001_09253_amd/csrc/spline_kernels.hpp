@@ -1022,6 +1022,56 @@ __device__ void eval_uniform_range(const double* __restrict__ x, const double* _
     }
 }
 
+// Per-query formulas of the evaluate sweep compared in "Benchmarks" ->
+// "Curve Interpolation" (the section's variants, as they map to a GPU):
+//   kHoisted:   newint with 1/(b - a) and (b - a)^2 computed once per interval
+//               (the default everywhere);
+//   kOrig:      newint__orig, inv_ba = 1/(b - a) formed for every query;
+//   kNoinv:     newint__noinv, a division by (b - a) for every query;
+//   kSplintDiv: the A, B, C, D form of "Fast Interpolation" with the
+//               divisions by h and by 6 per query (splint_one__div);
+//   kSplintMul: the same with the division by 6 as a multiplication
+//               (splint_one__mul).
+// (The paper's newint__vol variant is a C++ compiler-ordering trick with no
+// counterpart here.)
+enum NewintVariant : int { kHoisted = 0, kOrig = 1, kNoinv = 2, kSplintDiv = 3, kSplintMul = 4 };
+
+template <int V>
+__device__ __forceinline__ double interp_variant(double q, double a, double b, double u, double v, double up,
+                                                 double vp) {
+    if constexpr (V == kOrig || V == kNoinv) {
+        const double ba = b - a;
+        const double xa = q - a;
+        const double bx = b - q;
+        const double ba2 = ba * ba;
+        const double lower = xa * v + bx * u;
+        const double C = (xa * xa - ba2) * xa * vp;
+        const double D = (bx * bx - ba2) * bx * up;
+        if constexpr (V == kOrig) {
+            const double inv_ba = 1.0 / ba;
+            return (lower + (1.0 / 6.0) * (C + D)) * inv_ba;
+        } else {
+            return (lower + (1.0 / 6.0) * (C + D)) / ba;
+        }
+    } else {
+        const double hh = b - a;
+        const double A = (b - q) / hh;
+        const double B = (q - a) / hh;
+        const double cub = (A * A * A - A) * up + (B * B * B - B) * vp;
+        if constexpr (V == kSplintDiv) return A * u + B * v + cub * (hh * hh) / 6.0;
+        else return A * u + B * v + cub * (hh * hh) * (1.0 / 6.0);
+    }
+}
+
+// One query of interval [a, b] with the interval's hoisted 1/(b - a) (used
+// only by kHoisted).
+template <int V>
+__device__ __forceinline__ double interp_one(double q, double a, double b, double u, double v, double up, double vp,
+                                             double inv) {
+    if constexpr (V == kHoisted) return newint(q, a, b, u, v, up, vp, inv);
+    else return interp_variant<V>(q, a, b, u, v, up, vp);
+}
+
 // ---------------------------------------------------------------------------
 // One wavefront evaluates the uniform queries k0 .. k1-1 of a curve, all of
 // which lie in the intervals [j0, j1) of a block whose knots j (lo <= j <= j1)
@@ -1042,7 +1092,7 @@ __device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, d
     }
 }
 
-template <bool MIXED, bool PREFETCH = false>
+template <bool MIXED, bool PREFETCH = false, int VARIANT = kHoisted>
 __device__ void wave_eval_block(const double* sx, const double* sy, const double* so, const double* sinv,
                                 int32_t* bq, int lo, int rs, int j0, int j1, double x0, double xl, double h,
                                 double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane) {
@@ -1121,6 +1171,13 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         q0 = x0 + s0;
                         q1 = x0 + s1;
                     }
+                    if constexpr (VARIANT != kHoisted) {
+                        ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
+                        ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
+                        ob += 2 * kWave;
+                        kr += (double)(2 * kWave);
+                        continue;
+                    }
                     // a6: newint with the interval's 1/(b - a) and (b - a)^2
                     const double xa0 = q0 - av, bx0 = bv - q0;
                     const double xa1 = q1 - av, bx1 = bv - q1;
@@ -1140,10 +1197,16 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         const double st = kr * h;
                         q = x0 + st;
                     }
-                    const double xa = q - av, bx = bv - q;
-                    const double l = xa * v + bx * u;
-                    const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
-                    if (r + lane < ke) *ob = (l + (1.0 / 6.0) * cc) * inv;
+                    double val;
+                    if constexpr (VARIANT != kHoisted) {
+                        val = interp_variant<VARIANT>(q, av, bv, u, v, up, vp);
+                    } else {
+                        const double xa = q - av, bx = bv - q;
+                        const double l = xa * v + bx * u;
+                        const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
+                        val = (l + (1.0 / 6.0) * cc) * inv;
+                    }
+                    if (r + lane < ke) *ob = val;
                     ob += kWave;
                     kr += (double)kWave;
                 }
@@ -1169,8 +1232,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         if (k1 == m && m > 1 && lane == 0) {
             // query m-1 is x[n-1] itself (for m > 1), in interval t1
             const int t = t1;
-            out[m - 1] = newint(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
-                                so[t - rs], so[t + 1 - rs], sinv[t - j0]);
+            out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
+                                             so[t - rs], so[t + 1 - rs], sinv[t - j0]);
         }
         return;
     }
@@ -1186,8 +1249,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         while (tl + 1 <= t1 && sx[tl + 1 - lo] < q) ++tl;
         t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
         if (live) {
-            out[k] = newint(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
-                            so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
+            out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
+                                         so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
         }
     }
 }

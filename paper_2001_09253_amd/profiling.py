@@ -42,10 +42,23 @@ def _one(pattern):
     return hits[0]
 
 
+def _kernel_rows(prof_dir):
+    """Per-kernel calls and durations (ns) from a --stats CSV, or, without
+    one, from the run's rocpd database."""
+    hits = glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if hits:
+        with open(hits[0]) as f:
+            return list(csv.DictReader(f))
+    import sqlite3
+    con = sqlite3.connect(_one(os.path.join(prof_dir, "**", "*.db")))
+    q = ("select name, count(*), avg(duration), min(duration), max(duration) from kernels "
+         "group by name order by sum(duration) desc")
+    return [{"Name": r[0], "Calls": str(r[1]), "AverageNs": r[2], "MinNs": r[3], "MaxNs": r[4]}
+            for r in con.execute(q)]
+
+
 def stats(prof_dir, out_path, command):
-    path = _one(os.path.join(prof_dir, "**", "*kernel_stats.csv"))
-    with open(path) as f:
-        rows = list(csv.DictReader(f))
+    rows = _kernel_rows(prof_dir)
     lines = ["# rocprofv3 --kernel-trace --stats", "# command: " + command,
              "# kernel sources: " + kernel_source_hash(), "",
              "%-72s %7s %12s %12s %12s" % ("kernel", "calls", "avg_us", "min_us", "max_us")]
