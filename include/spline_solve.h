@@ -203,7 +203,8 @@ int spline_solve_uniform(const double *x, const double *y, int64_t n, double sta
 /* spline_solve_uniform with the evaluation formula chosen by `variant` (one of
  * the SOLVE_NEWINT_* / SOLVE_SPLINT_* values), for comparing the paper's
  * variants on the same build (a1-a5 unchanged).  It always takes the
- * wavefront-per-knot-block kernel, whatever the query density.  Arguments,
+ * dense-curve kernels (chosen as for spline_solve_uniform's dense
+ * path), whatever the query density.  Arguments,
  * layout, ownership and status as for spline_solve_uniform.  The variants
  * agree to rounding (a few ulp of max|y| at the query); SOLVE_NEWINT_HOISTED
  * matches spline_solve_uniform's dense path bit for bit.  Errors: E_ARG (null

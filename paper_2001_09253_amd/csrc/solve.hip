@@ -17,8 +17,10 @@
 // same kind of bound under 2^-60 max|y''|.  Curves shorter than the block
 // plus both halos are solved whole, exactly.
 //
-// Dense curves (many queries per interval) take one wavefront per block (or
-// per share of a block's queries); sparse curves one workgroup per block.
+// Dense curves (many queries per interval) take either a workgroup of four
+// wavefronts per block (one solves, all evaluate) or one wavefront per block
+// (each solves and evaluates), a block's queries cut into shares when there
+// are many; sparse curves take one workgroup per block.
 // Every y'' is written by the one block that owns it and every query is
 // evaluated once (a block's first and last query are found by an exact search
 // over the query index), so results do not depend on the grid.
@@ -194,6 +196,234 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
                                           k1, yq, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Dense curves, cooperative form: one workgroup of kCoopWaves wavefronts per
+// block of bk intervals (or per share of a block's queries).  The solve of a
+// block is one wavefront's work and its evaluation is cut among all of them:
+//   1. wavefront 0 finds the halo before the block, wavefront 1 the halo
+//      after it (adaptive, as above); wavefront 2 finds the first query above
+//      each knot of the block (a5), wavefront 3 the intervals' 1/(b - a);
+//   2. wavefront 0 solves rows [rs, re) (a1-a4) into LDS;
+//   3. the y'' the block owns are written and every wavefront evaluates its
+//      part of the block's queries (a6), interval by interval.
+// ---------------------------------------------------------------------------
+constexpr int kCoopWaves = 4;
+constexpr int kCoopThreads = kWave * kCoopWaves;
+
+struct CoopSmem {
+    double sx[kWave * kWaveSpanCH + 2];
+    double sy[kWave * kWaveSpanCH + 2];
+    double so[kWave * kWaveSpanCH + 2];
+    double inv[kMaxWaveBK];
+    int64_t kq[kMaxWaveBK + 1];  // kq[i]: first query above knot j0 + i (0 and m at the curve's ends)
+    int rs, re;
+};
+
+// Queries k0 .. k1-1 of the block [j0, j1) (all inside it), by one
+// wavefront, with the block's knots, values and y'' in LDS and kq as above.
+// Query k lies in interval t exactly when kq[t - j0] <= k < kq[t + 1 - j0].
+template <int VARIANT>
+__device__ __forceinline__ void coop_eval(const CoopSmem& sm, int lo, int rs, int j0, int j1, double x0, double xl,
+                                          double h, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out,
+                                          int lane) {
+    const int nbk = j1 - j0;
+    int ca = 0, cb = 0;
+    {
+        const int i = 1 + lane;  // interior knots of the block (nbk <= kMaxWaveBK < kWave)
+        const bool in = i < nbk;
+        const int64_t v = in ? sm.kq[i] : 0;
+        ca = __popcll(__ballot(in && v <= k0));
+        cb = __popcll(__ballot(in && v <= k1 - 1));
+    }
+    const int t0 = j0 + ca;
+    const int t1 = j0 + cb;
+    const int nt = t1 - t0 + 1;
+    const double* sx = sm.sx;
+    const double* sy = sm.sy;
+    const double* so = sm.so;
+    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
+        const double kl0 = (double)k0 + (double)lane;
+        double* __restrict__ o = out + k0 + lane;
+        for (int t = t0; t <= t1; ++t) {
+            const int64_t ka = (t == t0) ? k0 : sm.kq[t - j0];
+            const int64_t kb = (t == t1) ? k1 : sm.kq[t + 1 - j0];
+            if (ka >= kb) continue;
+            const double av = sx[t - lo], bv = sx[t + 1 - lo];
+            const double u = sy[t - lo], v = sy[t + 1 - lo];
+            const double up = so[t - rs], vp = so[t + 1 - rs];
+            const double inv = sm.inv[t - j0];
+            const double ba = bv - av;
+            const double ba2 = ba * ba;
+            const int ks = __builtin_amdgcn_readfirstlane((int)(ka - k0));  // uniform: loop bounds in SGPRs
+            const int ke = __builtin_amdgcn_readfirstlane((int)(kb - k0));
+            // kr = k0 + lane + r is the query index k exactly, so x0 + kr*h
+            // (one multiply, then one add) is uniform_query(.., k) bit for bit;
+            // query m-1 (x[n-1] itself) is patched below
+            double kr = kl0 + (double)ks;
+            double* __restrict__ ob = o + ks;
+            int r = ks;
+            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
+                double q0, q1;
+                {
+#pragma clang fp contract(off)
+                    const double s0 = kr * h;
+                    const double s1 = (kr + (double)kWave) * h;
+                    q0 = x0 + s0;
+                    q1 = x0 + s1;
+                }
+                if constexpr (VARIANT == kHoisted) {
+                    // a6: newint with the interval's 1/(b - a) and (b - a)^2
+                    const double xa0 = q0 - av, bx0 = bv - q0;
+                    const double xa1 = q1 - av, bx1 = bv - q1;
+                    const double l0 = xa0 * v + bx0 * u;
+                    const double l1 = xa1 * v + bx1 * u;
+                    const double c0 = (xa0 * xa0 - ba2) * xa0 * vp + (bx0 * bx0 - ba2) * bx0 * up;
+                    const double c1 = (xa1 * xa1 - ba2) * xa1 * vp + (bx1 * bx1 - ba2) * bx1 * up;
+                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
+                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                } else {
+                    ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
+                    ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
+                }
+                ob += 2 * kWave;
+                kr += (double)(2 * kWave);
+            }
+            for (; r < ke; r += kWave) {
+                double q;
+                {
+#pragma clang fp contract(off)
+                    const double st = kr * h;
+                    q = x0 + st;
+                }
+                const double val = interp_one<VARIANT>(q, av, bv, u, v, up, vp, inv);
+                if (r + lane < ke) *ob = val;
+                ob += kWave;
+                kr += (double)kWave;
+            }
+        }
+        if (k1 == m && m > 1 && lane == 0) {
+            const int t = t1;  // query m-1 is x[n-1] itself, in the last interval
+            out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
+                                             so[t - rs], so[t + 1 - rs], sm.inv[t - j0]);
+        }
+        return;
+    }
+    // fewer queries per interval: 64 consecutive queries at a time, each lane
+    // walking from the wavefront's current interval
+    int t = t0;
+    for (int64_t kc = k0; kc < k1; kc += kWave) {
+        const int64_t k = kc + lane;
+        const bool live = k < k1;
+        const double q = uniform_query(x0, xl, h, m, live ? k : k1 - 1);
+        int tl = t;
+        while (tl + 1 <= t1 && sm.kq[tl + 1 - j0] <= (live ? k : k1 - 1)) ++tl;
+        t = __shfl(tl, kWave - 1);
+        if (live)
+            out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
+                                         so[tl - rs], so[tl + 1 - rs], sm.inv[tl - j0]);
+    }
+}
+
+template <int VARIANT>
+__global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int bk, int shares) {
+    __shared__ CoopSmem sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    // each wavefront's role rotates with the workgroup, so that the solves of
+    // the workgroups sharing a compute unit fall on different SIMDs
+    const int wid = (tid / kWave + (int)blockIdx.x) & (kCoopWaves - 1);
+    const int n = (int)n64;
+    const int64_t blk = blockIdx.x / shares;
+    const int sh = (int)(blockIdx.x - blk * shares);
+    const int j0 = (int)(blk * bk);
+    const int j1 = min(j0 + bk, n - 1);  // intervals [j0, j1)
+    const int nbk = j1 - j0;
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    // 1. knots and values j0 - 64 .. j1 + 64 staged in one round (every row
+    // an adaptive halo can reach); then the halos, the first query above each
+    // knot of the block and the intervals' 1/(b - a), from LDS
+    const int wlo = max(j0 - kWave, 0);
+    const int whi = min(j1 + kWave, n - 1);
+    for (int j = wlo + tid; j <= whi; j += kCoopThreads) {
+        sm.sx[j - wlo] = x[j];
+        sm.sy[j - wlo] = y[j];
+    }
+    __syncthreads();
+    const double* xs = sm.sx - wlo;  // xs[j] is knot j for j in [wlo, whi]
+    if (wid == 0) {
+        const int rs = halo_start(xs, j0, kHaloEps, kHalo, lane);
+        if (lane == 0) sm.rs = rs;
+    } else if (wid == 1) {
+        const int re = halo_end(xs, n, j1, kHaloEps, kHalo, lane);
+        if (lane == 0) sm.re = re;
+    } else if (wid == 2) {
+        if (lane <= nbk) {
+            const int j = j0 + lane;
+            const double rh = (m > 1) ? 1.0 / h : 0.0;
+            sm.kq[lane] = (j == 0) ? 0 : (j == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, xs[j]);
+        }
+    } else {
+        if (lane < nbk) sm.inv[lane] = 1.0 / (xs[j0 + lane + 1] - xs[j0 + lane]);
+    }
+    __syncthreads();
+    const int rs = sm.rs;
+    const int re = sm.re;
+    const int lo = max(rs - 1, 0);
+    const int hi = min(re, n - 1);
+    // the rows an adaptive halo chose lie in the staged window; the uniform
+    // fallback halo stages its own (knot j then at [j - lo])
+    const bool staged = lo >= wlo && hi <= whi;
+    const int base = staged ? wlo : lo;
+    // 2. a1-a4 over rows [rs, re) (at most 64 * kWaveSpanCH; the per-row
+    // scaling keeps the scan inside the double range without normalising)
+    if (wid == 0) {
+        bool bad;
+        double* bx = sm.sx + (lo - base);
+        double* by = sm.sy + (lo - base);
+        if (staged && re - rs <= kWave)
+            bad = build_span<kWave, 1, true, SoloGroup, false, true>(x, y, n, rs, re, sd, ed, nullptr, nullptr, bx,
+                                                                      nullptr, nullptr, SoloGroup{}, lane, by, sm.so);
+        else if (staged && re - rs <= 2 * kWave)
+            bad = build_span<kWave, 2, true, SoloGroup, false, true>(x, y, n, rs, re, sd, ed, nullptr, nullptr, bx,
+                                                                      nullptr, nullptr, SoloGroup{}, lane, by, sm.so);
+        else if (staged)
+            bad = build_span<kWave, kWaveSpanCH, true, SoloGroup, false, true>(x, y, n, rs, re, sd, ed, nullptr,
+                                                                                nullptr, bx, nullptr, nullptr,
+                                                                                SoloGroup{}, lane, by, sm.so);
+        else
+            bad = build_span<kWave, kWaveSpanCH, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr,
+                                                                          bx, nullptr, nullptr, SoloGroup{}, lane, by,
+                                                                          sm.so);
+        if (bad && status && lane == 0) atomicMin(status, kStatusOrder);
+    }
+    __syncthreads();
+    if (ypp && sh == 0) {
+        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+        for (int j = j0 + tid; j < jend; j += kCoopThreads) ypp[j] = sm.so[j - rs];
+    }
+    // 3. this wavefront's part of the block's queries (a5: kq[0] .. kq[nbk])
+    const int64_t ka = sm.kq[0];
+    const int64_t len = max(sm.kq[nbk] - ka, (int64_t)0);
+    const int64_t parts = (int64_t)shares * kCoopWaves;
+    const int64_t p = (int64_t)sh * kCoopWaves + wid;
+    int64_t per, rem;
+    if (len < 0x7fffffffLL && parts < 0x7fffffffLL) {  // 32-bit division where it fits
+        per = (uint32_t)len / (uint32_t)parts;
+        rem = (uint32_t)len - (uint32_t)per * (uint32_t)parts;
+    } else {
+        per = len / parts;
+        rem = len % parts;
+    }
+    const int64_t k0 = ka + per * p + min(p, rem);
+    const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
+    if (k0 >= k1) return;
+    coop_eval<VARIANT>(sm, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq, lane);
+}
+
 static int cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -251,10 +481,48 @@ static int launch_waves_solve(const double* x, const double* y, int64_t n, doubl
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
+// Dense curves: about kCoopBlockQ queries per block (at least one interval,
+// at most kMaxWaveBK), a block's queries cut into shares of at most
+// kCoopShareQ (each share's workgroup solves the block's rows again).
+constexpr double kCoopBlockQ = 2048.0;
+constexpr double kCoopShareQ = 5460.0;
+
+template <int VARIANT>
+static int launch_coop_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
+                             double* yq, double* ypp, int32_t* status, hipStream_t s, double block_q = kCoopBlockQ,
+                             double share_q = kCoopShareQ) {
+    const double queries_per_knot = (double)m / (double)(n - 1);
+    const int bk = (int)std::min<double>(kMaxWaveBK, std::max(1.0, std::round(block_q / queries_per_knot)));
+    const int64_t nblocks = (n - 1 + bk - 1) / bk;
+    const double per_block = queries_per_knot * bk;
+    const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / share_q)));
+    if (nblocks * shares > 0x7fffffffLL) return SOLVE_E_SIZE;
+    solve_coop_kernel<VARIANT><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
+                                                                                    status, bk, shares);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
+// Dense curves: the cooperative kernel while the wavefront-per-block form
+// would leave the device short of wavefronts (every solve's latency then
+// sits on the critical path; sharing one solve among four wavefronts
+// shortens it) and for very dense queries (one solve per 2 shares instead of
+// one per share); otherwise one wavefront per block, which keeps more solves
+// in flight per compute unit.
+template <int VARIANT>
+static int launch_dense(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
+                        double* ypp, int32_t* status, hipStream_t s) {
+    const double queries_per_knot = (double)m / (double)(n - 1);
+    const double bk = std::min<double>(kMaxWaveBK, std::max(2.0, std::round(2048.0 / queries_per_knot)));
+    const double wave_items = std::ceil((double)(n - 1) / bk) * std::max(1.0, std::ceil(queries_per_knot * bk / 2730.0));
+    if (wave_items <= 32.0 * cu_count() || queries_per_knot >= 1024.0)
+        return launch_coop_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    return launch_waves_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, s);
+}
+
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
-    if (queries_per_knot >= 48.0) return launch_waves_solve<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    if (queries_per_knot >= 48.0) return launch_dense<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
     if (queries_per_knot * 64 >= 1024.0) return launch_blocks<64>(x, y, n, sd, ed, m, yq, ypp, status, s);
     return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, s);
 }
@@ -279,15 +547,15 @@ extern "C" int spline_solve_uniform_variant(const double* x, const double* y, in
     hipStream_t s = (hipStream_t)stream;
     switch (variant) {
         case SOLVE_NEWINT_HOISTED:
-            return launch_waves_solve<kHoisted>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kHoisted>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         case SOLVE_NEWINT_ORIG:
-            return launch_waves_solve<kOrig>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kOrig>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         case SOLVE_NEWINT_NOINV:
-            return launch_waves_solve<kNoinv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kNoinv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         case SOLVE_SPLINT_DIV:
-            return launch_waves_solve<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         case SOLVE_SPLINT_MUL:
-            return launch_waves_solve<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         default:
             return SOLVE_E_ARG;
     }

@@ -407,41 +407,44 @@ __device__ __forceinline__ double wave_excl_prefix_prod(double v) {
 // and the halo on each side is the shortest (at most 63 rows) that takes its
 // product below eps, or the uniform hmax rows where F <= 2/3 and G <= 1/2
 // always suffice (then the wavefront's capacity must hold them).  Every lane
-// calls this and receives the same rs, re.
+// calls this and receives the same rs, re; halo_start and halo_end are its two
+// sides (rs from the rows before j0, re from the rows after j1).
+__device__ __forceinline__ int halo_start(const double* __restrict__ x, int j0, double eps, int hmax, int lane) {
+    if (j0 <= 0) return 0;
+    const int k = j0 - lane;
+    double f = 0.0;  // rows at or before the first: nothing to drop
+    if (k >= 1) {
+        const double a = x[k] - x[k - 1];
+        const double c = x[k + 1] - x[k];
+        f = a / (1.5 * a + 2.0 * c);
+    }
+    const double p = wave_excl_prefix_prod(f);
+    const bool ok = (k <= 0) || (0.75 * p <= eps);  // NaN never passes
+    const uint64_t b = __ballot(ok);
+    const int rs = b ? j0 - (int)(__ffsll((long long)b) - 1) : j0 - hmax;
+    return max(rs, 0);
+}
+
+__device__ __forceinline__ int halo_end(const double* __restrict__ x, int n, int j1, double eps, int hmax, int lane) {
+    if (j1 >= n - 1) return n;
+    const int k = j1 + lane;
+    double g = 0.0;  // rows at or past the last: nothing to drop
+    if (k <= n - 2) {
+        const double a = x[k] - x[k - 1];
+        const double c = x[k + 1] - x[k];
+        g = c / (1.5 * a + 2.0 * c);
+    }
+    const double q = wave_excl_prefix_prod(g);
+    const bool ok = (k + 1 >= n) || (0.5 * q <= eps);
+    const uint64_t b = __ballot(ok);
+    const int re = b ? j1 + 1 + (int)(__ffsll((long long)b) - 1) : j1 + 1 + hmax;
+    return min(re, n);
+}
+
 __device__ __forceinline__ void adaptive_halo(const double* __restrict__ x, int n, int j0, int j1, double eps,
                                               int hmax, int lane, int* rs_out, int* re_out) {
-    int rs = 0;
-    if (j0 > 0) {
-        const int k = j0 - lane;
-        double f = 0.0;  // rows at or before the first: nothing to drop
-        if (k >= 1) {
-            const double a = x[k] - x[k - 1];
-            const double c = x[k + 1] - x[k];
-            f = a / (1.5 * a + 2.0 * c);
-        }
-        const double p = wave_excl_prefix_prod(f);
-        const bool ok = (k <= 0) || (0.75 * p <= eps);  // NaN never passes
-        const uint64_t b = __ballot(ok);
-        rs = b ? j0 - (int)(__ffsll((long long)b) - 1) : max(0, j0 - hmax);
-        rs = max(rs, 0);
-    }
-    int re = n;
-    if (j1 < n - 1) {
-        const int k = j1 + lane;
-        double g = 0.0;  // rows at or past the last: nothing to drop
-        if (k <= n - 2) {
-            const double a = x[k] - x[k - 1];
-            const double c = x[k + 1] - x[k];
-            g = c / (1.5 * a + 2.0 * c);
-        }
-        const double q = wave_excl_prefix_prod(g);
-        const bool ok = (k + 1 >= n) || (0.5 * q <= eps);
-        const uint64_t b = __ballot(ok);
-        re = b ? j1 + 1 + (int)(__ffsll((long long)b) - 1) : min(n, j1 + 1 + hmax);
-        re = min(re, n);
-    }
-    *rs_out = rs;
-    *re_out = re;
+    *rs_out = halo_start(x, j0, eps, hmax, lane);
+    *re_out = halo_end(x, n, j1, eps, hmax, lane);
 }
 
 // Cross-workgroup signalling.  On a multi-XCD device an agent-scope acquire
@@ -535,11 +538,13 @@ struct SoloGroup {  // the group holds every row of the curve
 //          for y and for the result; with lds_y, x and y are staged in one
 //          load round and both stay staged (knot j at [j - max(rs-1, 0)]);
 //          with lds_out the result is left there as lds_out[i - rs]
+//   STAGED: the caller has already staged x and y that way (lds_y required)
+//          and synchronised
 // Requires 3 <= n and re - rs <= NT*CH.  Writes ypp[rs..re) when ypp is not
 // null; the group that owns row 0 writes *status (if status).  Returns
 // whether the knots were found unordered.
 // ---------------------------------------------------------------------------
-template <int NT, int CH, bool WAVE_ONLY, typename Cross, bool NORM = true>
+template <int NT, int CH, bool WAVE_ONLY, typename Cross, bool NORM = true, bool STAGED = false>
 __device__ __forceinline__ bool build_span(const double* __restrict__ x, const double* __restrict__ y, int n, int rs, int re,
                            double sd, double ed, double* __restrict__ ypp, int32_t* __restrict__ status,
                            double* lds, Fwd* lds_f, Bwd* lds_b, const Cross& cross, int tid,
@@ -561,11 +566,13 @@ __device__ __forceinline__ bool build_span(const double* __restrict__ x, const d
     // a1: widths and validation (x staged through LDS, coalesced).
     const bool split = lds_y != nullptr;
     double* sy = split ? lds_y : lds;
-    for (int i = lo + tid; i <= hi; i += NT) {
-        lds[i - lo] = x[i];
-        if (split) sy[i - lo] = y[i];
+    if constexpr (!STAGED) {
+        for (int i = lo + tid; i <= hi; i += NT) {
+            lds[i - lo] = x[i];
+            if (split) sy[i - lo] = y[i];
+        }
+        group_sync<WAVE_ONLY>();
     }
-    group_sync<WAVE_ONLY>();
     bool bad = false;
     double w[CH];
     double d[CH];

@@ -208,7 +208,8 @@ def test_eval_points_matches_oracle(kind):
 
 
 SOLVE_CASES = [(3, 5), (13, 2048), (100, 7), (513, 100000), (1024, 1), (1025, 4096), (4097, 333),
-               (13000, 2048000), (20000, 20000), (65536, 1 << 20), (300000, 1000), (250, 3000000)]
+               (13000, 2048000), (20000, 20000), (65536, 1 << 20), (300000, 1000), (250, 3000000),
+               (300001, 19200000)]
 
 
 @pytest.mark.parametrize("n,m", SOLVE_CASES)
