@@ -239,7 +239,9 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
  * small), else 255 intervals plus 128 halo rows on either side, whose dropped
  * coupling is below 4.5 (2/3)^128 of max|y''| -- and evaluates its queries;
  * wavefronts never wait on one another.  With tuning.fused = 2 the curves of
- * up to 256 knots are solved by a first launch instead.
+ * up to 256 knots are solved by a first launch instead; with tuning.fused = 3
+ * a work item is a workgroup of four wavefronts, one of which solves the span
+ * while all four evaluate its queries.
  * ========================================================================== */
 
 typedef struct spline_plan spline_plan;
@@ -251,7 +253,11 @@ typedef struct spline_plan spline_plan;
  * persistent workgroups per compute unit (1..64) striding over the items;
  * fused = 1: one launch, every work item solves its own span; fused = 2: two
  * launches, curves of up to 256 knots solved first (16 lanes per curve, four
- * curves per wavefront) and their work items only evaluate. */
+ * curves per wavefront) and their work items only evaluate; fused = 3: one
+ * launch, one workgroup of four wavefronts per work item (block must be 256,
+ * grid_per_cu is ignored; queries_per_tile is the largest share of one
+ * workgroup), one wavefront solving the span into LDS and all four
+ * evaluating a quarter of the share each. */
 typedef struct {
     int32_t block;
     int32_t queries_per_tile;

@@ -343,6 +343,138 @@ static int launch_waves_any(int ch, const BatchDevArgs& a, const spline_tuning& 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative form (tuning.fused = 3): one workgroup of four wavefronts per
+// work item.  One wavefront (its role rotates with the workgroup) solves the
+// item's span into the workgroup's LDS, then all four evaluate a quarter of
+// the item's queries each.  An item's latency is then one solve plus a
+// quarter of its evaluation, so the last items the dispatcher starts finish
+// soon after the others.
+// ---------------------------------------------------------------------------
+constexpr int kCoopItemWaves = 4;
+
+template <int CH>
+struct CoopItemSmem {
+    static constexpr int kRows = kWave * CH;
+    double sx[kRows + 2];
+    double sy[kRows + 2];
+    double so[kRows + 2];
+    double inv[kRows];
+    int32_t bq[kCoopItemWaves][kRows + 1];
+    int32_t bad;
+};
+
+template <int CH, bool BUILD, bool MIXED>
+__global__ __launch_bounds__(kCoopItemWaves * kWave) void coop_items_kernel(BatchDevArgs a) {
+    __shared__ CoopItemSmem<CH> sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int role = (tid / kWave + (int)blockIdx.x) & (kCoopItemWaves - 1);
+    constexpr int NT = kCoopItemWaves * kWave;
+    const WaveItem it = a.witems[blockIdx.x];
+    const int i = it.inst;
+    const int64_t ko = it.ko;
+    const int n = it.n;
+    const int64_t qo = it.qo;
+    const int64_t m = it.m;
+    const double* __restrict__ x = a.x + ko;
+    const double* __restrict__ y = a.y + ko;
+    const int j0 = it.j0;
+    const int j1 = it.j1;
+    const bool reporter = j0 == 0 && it.s == 0;  // fills the outputs of a bad curve with NaN
+    const double nan = __builtin_nan("");
+    int rs = 0, re = n;
+    if (!BUILD || n <= a.prebuilt_max_n) {
+        // y'' from phase 1: stage knots lo..j1 (lo = max(j0 - 1, 0))
+        if (a.bad[i]) {
+            if (reporter && it.S > 0)
+                for (int64_t k = tid; k < m; k += NT) a.yq[qo + k] = nan;
+            return;
+        }
+        if (it.S == 0) return;
+        rs = j0;
+        const int lo_ = max(j0 - 1, 0);
+        const int cnt = j1 - lo_ + 1;
+        for (int j = tid; j < cnt; j += NT) {
+            sm.sx[j] = x[lo_ + j];
+            sm.sy[j] = y[lo_ + j];
+            if (lo_ + j >= rs) sm.so[lo_ + j - rs] = a.ypp[ko + lo_ + j];
+        }
+    } else {
+        // a1-a4 over the item's span by one wavefront (as in the
+        // wavefront-per-item form), the others waiting at the barrier
+        const bool whole = j0 == 0 && j1 == n - 1;
+        rs = whole ? 0 : max(0, j0 - kBatchHalo);
+        re = whole ? n : min(n, j1 + 1 + kBatchHalo);
+        if (role == 0) {
+            bool bad = build_span<kWave, CH, true, SoloGroup, false>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr,
+                                                                      nullptr, sm.sx, nullptr, nullptr, SoloGroup{},
+                                                                      lane, sm.sy, sm.so);
+            if (!whole) {
+                bool b = false;
+                for (int j = 1 + lane; j < n; j += kWave) b |= !(x[j] > x[j - 1]);
+                bad = bad || (__ballot(b) != 0ull);
+            }
+            if (lane == 0) sm.bad = bad ? 1 : 0;
+        }
+        __syncthreads();
+        if (sm.bad) {
+            if (reporter) {
+                if (a.ypp)
+                    for (int j = tid; j < n; j += NT) a.ypp[ko + j] = nan;
+                if (it.S > 0)
+                    for (int64_t k = tid; k < m; k += NT) a.yq[qo + k] = nan;
+                if (a.status && tid == 0) a.status[i] = kStatusOrder;
+            }
+            return;
+        }
+        if (reporter && a.status && tid == 0) a.status[i] = kStatusOk;
+        if (it.s == 0 && a.ypp) {
+            const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+            for (int j = j0 + tid; j < jend; j += NT) a.ypp[ko + j] = sm.so[j - rs];
+        }
+        if (it.S == 0) return;
+    }
+    const int lo = max(rs - 1, 0);
+    __syncthreads();
+    for (int t = j0 + tid; t < j1; t += NT) sm.inv[t - j0] = 1.0 / (sm.sx[t + 1 - lo] - sm.sx[t - lo]);
+    __syncthreads();
+    // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the
+    // first block); this item takes share s of S of them, cut in four
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    const double rh = (m > 1) ? 1.0 / h : 0.0;
+    const int64_t ka = (j0 == 0) ? 0 : first_query_above_r(x0, xl, h, rh, m, sm.sx[j0 - lo]);
+    const int64_t kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, sm.sx[j1 - lo]);
+    const int64_t len = max(kb - ka, (int64_t)0);
+    const int64_t parts = (int64_t)it.S * kCoopItemWaves;
+    const int64_t p = (int64_t)it.s * kCoopItemWaves + role;
+    const int64_t per = len / parts;
+    const int64_t rem = len % parts;
+    const int64_t k0 = ka + per * p + min(p, rem);
+    const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
+    if (k0 >= k1) return;
+    wave_eval_block<MIXED>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq[tid / kWave], lo, rs, j0, j1, x0, xl, h, rh, m, k0,
+                           k1, a.yq + qo, lane);
+}
+
+template <bool BUILD, bool MIXED>
+static int launch_coop_any(int ch, const BatchDevArgs& a, hipStream_t s) {
+    if (a.n_witems < 1) return SOLVE_OK;
+    if (a.n_witems > 0x7fffffffLL) return SOLVE_E_SIZE;
+    const unsigned g = (unsigned)a.n_witems;
+    constexpr int NT = kCoopItemWaves * kWave;
+    switch (ch) {
+        case 1: coop_items_kernel<1, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        case 2: coop_items_kernel<2, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        case 3: coop_items_kernel<3, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        case 4: coop_items_kernel<4, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        case kWaveMaxCH: coop_items_kernel<kWaveMaxCH, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        default: return SOLVE_E_ARG;
+    }
+}
+
 spline_tuning default_tuning() {
     spline_tuning t;
     t.block = 256;
@@ -353,7 +485,8 @@ spline_tuning default_tuning() {
 }
 
 bool valid_tuning(const spline_tuning& t) {
-    return (t.fused == 1 || t.fused == 2) && (t.block == 64 || t.block == 128 || t.block == 256) &&
+    return (t.fused == 1 || t.fused == 2 || (t.fused == 3 && t.block == 256)) &&
+           (t.block == 64 || t.block == 128 || t.block == 256) &&
            t.queries_per_tile >= 64 && t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
 }
 
@@ -544,9 +677,17 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     // phase 2: the kernel holds the span solve only if some curve needs it
     const bool build = max_n_ > prebuilt_max_n_;
     int rc;
-    if (mixed) rc = launch_waves_any<false, true>(wave_ch_, a, tuning_, num_cu_, s);
-    else if (build) rc = launch_waves_any<true, false>(wave_ch_, a, tuning_, num_cu_, s);
-    else rc = launch_waves_any<false, false>(wave_ch_, a, tuning_, num_cu_, s);
+    if (tuning_.fused == 3) {
+        if (mixed) rc = launch_coop_any<false, true>(wave_ch_, a, s);
+        else if (build) rc = launch_coop_any<true, false>(wave_ch_, a, s);
+        else rc = launch_coop_any<false, false>(wave_ch_, a, s);
+    } else if (mixed) {
+        rc = launch_waves_any<false, true>(wave_ch_, a, tuning_, num_cu_, s);
+    } else if (build) {
+        rc = launch_waves_any<true, false>(wave_ch_, a, tuning_, num_cu_, s);
+    } else {
+        rc = launch_waves_any<false, false>(wave_ch_, a, tuning_, num_cu_, s);
+    }
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
@@ -753,6 +894,7 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
         for (int block : {64, 256})
             for (int cap : {2048, 4096, 8192})
                 for (int gpc : {0, 16}) cands.push_back(spline_tuning{block, cap, gpc, fused});
+    for (int cap : {4096, 8192, 16384}) cands.push_back(spline_tuning{256, cap, 0, 3});
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;
     hipEvent_t e0, e1;
