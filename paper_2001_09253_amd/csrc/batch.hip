@@ -187,6 +187,26 @@ struct WaveSmem {
     int32_t bq[kRows + 1];
 };
 
+// One wavefront's solve of rows [rs, re) (at most 64 CH), compiled for the
+// fewest rows per lane that hold the span.
+template <int CH>
+__device__ __forceinline__ bool build_any(const double* __restrict__ x, const double* __restrict__ y, int n, int rs,
+                                          int re, double sd, double ed, double* sx, double* sy, double* so,
+                                          int lane) {
+    if constexpr (CH > 1) {
+        if (re - rs <= kWave)
+            return build_span<kWave, 1, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sx,
+                                                                nullptr, nullptr, SoloGroup{}, lane, sy, so);
+    }
+    if constexpr (CH > 2) {
+        if (re - rs <= 2 * kWave)
+            return build_span<kWave, 2, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sx,
+                                                                nullptr, nullptr, SoloGroup{}, lane, sy, so);
+    }
+    return build_span<kWave, CH, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sx, nullptr,
+                                                         nullptr, SoloGroup{}, lane, sy, so);
+}
+
 // One wave item.  All 64 lanes of the wavefront call this.  BUILD: items of
 // curves past a.prebuilt_max_n knots solve their span here; curves up to that
 // length were built by phase 1.
@@ -246,9 +266,7 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
         re = whole ? n : min(n, j1 + 1 + kBatchHalo);
         // (at most 512 rows: the per-row scaling keeps the scan's entries
         // inside the double range without normalising)
-        bool bad = build_span<kWave, CH, true, SoloGroup, false>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr,
-                                                                  nullptr, sm.sx, nullptr, nullptr, SoloGroup{}, lane,
-                                                                  sm.sy, sm.so);
+        bool bad = build_any<CH>(x, y, n, rs, re, a.sd[i], a.ed[i], sm.sx, sm.sy, sm.so, lane);
         if (!whole) {
             bool b = false;
             for (int j = 1 + lane; j < n; j += kWave) b |= !(x[j] > x[j - 1]);
@@ -407,9 +425,7 @@ __global__ __launch_bounds__(kCoopItemWaves * kWave) void coop_items_kernel(Batc
         rs = whole ? 0 : max(0, j0 - kBatchHalo);
         re = whole ? n : min(n, j1 + 1 + kBatchHalo);
         if (role == 0) {
-            bool bad = build_span<kWave, CH, true, SoloGroup, false>(x, y, n, rs, re, a.sd[i], a.ed[i], nullptr,
-                                                                      nullptr, sm.sx, nullptr, nullptr, SoloGroup{},
-                                                                      lane, sm.sy, sm.so);
+            bool bad = build_any<CH>(x, y, n, rs, re, a.sd[i], a.ed[i], sm.sx, sm.sy, sm.so, lane);
             if (!whole) {
                 bool b = false;
                 for (int j = 1 + lane; j < n; j += kWave) b |= !(x[j] > x[j - 1]);

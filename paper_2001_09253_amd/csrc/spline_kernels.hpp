@@ -1138,8 +1138,10 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         double* __restrict__ o = out + k0 + lane;
         // interval c's constants (and, with PREFETCH, interval c+1's read
         // from LDS while interval c is evaluated)
-        int ke = bq[0];
-        int kn = bq[1];
+        // (bq is uniform: its entries are read into scalar registers, so the
+        // loops below branch on scalars)
+        int ke = __builtin_amdgcn_readfirstlane(bq[0]);
+        int kn = __builtin_amdgcn_readfirstlane(bq[1]);
         double av = sx[t0 - lo], bv = sx[t0 + 1 - lo];
         double u = sy[t0 - lo], v = sy[t0 + 1 - lo];
         double up = so[t0 - rs], vp = so[t0 + 1 - rs];
@@ -1150,7 +1152,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
             double av_n = 0.0, bv_n = 0.0, u_n = 0.0, v_n = 0.0, up_n = 0.0, vp_n = 0.0, inv_n = 0.0;
             const int tn = min(t0 + c + 1, t1);
             if constexpr (PREFETCH) {
-                kn = bq[min(c + 2, nt)];
+                kn = __builtin_amdgcn_readfirstlane(bq[min(c + 2, nt)]);
                 av_n = sx[tn - lo];
                 bv_n = sx[tn + 1 - lo];
                 u_n = sy[tn - lo];
@@ -1219,7 +1221,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                 }
             }
             if constexpr (!PREFETCH) {
-                kn = bq[min(c + 2, nt)];
+                kn = __builtin_amdgcn_readfirstlane(bq[min(c + 2, nt)]);
                 av_n = sx[tn - lo];
                 bv_n = sx[tn + 1 - lo];
                 u_n = sy[tn - lo];
