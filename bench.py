@@ -367,7 +367,7 @@ def main():
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy"])
     ap.add_argument("--variant", default=None,
-                    choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul"],
+                    choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul", "horner"],
                     help="single-curve workloads: time this evaluation formula on the one-launch kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

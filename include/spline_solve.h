@@ -199,9 +199,11 @@ int spline_solve_uniform(const double *x, const double *y, int64_t n, double sta
 #define SOLVE_NEWINT_NOINV 2   /* newint dividing by (b-a) per query              */
 #define SOLVE_SPLINT_DIV 3     /* the A,B,C,D form ("Fast Interpolation"), /6     */
 #define SOLVE_SPLINT_MUL 4     /* the same with the /6 as a multiplication        */
+#define SOLVE_HORNER 5         /* not the paper's: power-basis coefficients per    */
+                               /* interval, Horner's rule in q - x_j              */
 
 /* spline_solve_uniform with the evaluation formula chosen by `variant` (one of
- * the SOLVE_NEWINT_* / SOLVE_SPLINT_* values), for comparing the paper's
+ * the SOLVE_NEWINT_* / SOLVE_SPLINT_* / SOLVE_HORNER values), for comparing the paper's
  * variants on the same build (a1-a5 unchanged).  It always takes the
  * dense-curve kernels (chosen as for spline_solve_uniform's dense
  * path), whatever the query density.  Arguments,

@@ -108,8 +108,9 @@ NEWINT_ORIG = 1
 NEWINT_NOINV = 2
 SPLINT_DIV = 3
 SPLINT_MUL = 4
+HORNER = 5  # not one of the paper's variants
 VARIANTS = {"newint": NEWINT_HOISTED, "newint__orig": NEWINT_ORIG, "newint__noinv": NEWINT_NOINV,
-            "splint_one__div": SPLINT_DIV, "splint_one__mul": SPLINT_MUL}
+            "splint_one__div": SPLINT_DIV, "splint_one__mul": SPLINT_MUL, "horner": HORNER}
 
 
 def spline_solve_uniform_variant(x, y, start_deriv, end_deriv, m, variant, yq, ypp=None, status=None, stream=None):

@@ -254,6 +254,8 @@ __device__ __forceinline__ void coop_eval(const CoopSmem& sm, int lo, int rs, in
             const double inv = sm.inv[t - j0];
             const double ba = bv - av;
             const double ba2 = ba * ba;
+            Cubic4 cf{};
+            if constexpr (VARIANT == kHorner) cf = power_coeffs(av, bv, u, v, up, vp, inv);
             const int ks = __builtin_amdgcn_readfirstlane((int)(ka - k0));  // uniform: loop bounds in SGPRs
             const int ke = __builtin_amdgcn_readfirstlane((int)(kb - k0));
             // kr = k0 + lane + r is the query index k exactly, so x0 + kr*h
@@ -281,6 +283,9 @@ __device__ __forceinline__ void coop_eval(const CoopSmem& sm, int lo, int rs, in
                     const double c1 = (xa1 * xa1 - ba2) * xa1 * vp + (bx1 * bx1 - ba2) * bx1 * up;
                     ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
                     ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                } else if constexpr (VARIANT == kHorner) {
+                    ob[0] = horner(cf, q0 - av);
+                    ob[kWave] = horner(cf, q1 - av);
                 } else {
                     ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
                     ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
@@ -295,7 +300,9 @@ __device__ __forceinline__ void coop_eval(const CoopSmem& sm, int lo, int rs, in
                     const double st = kr * h;
                     q = x0 + st;
                 }
-                const double val = interp_one<VARIANT>(q, av, bv, u, v, up, vp, inv);
+                double val;
+                if constexpr (VARIANT == kHorner) val = horner(cf, q - av);
+                else val = interp_one<VARIANT>(q, av, bv, u, v, up, vp, inv);
                 if (r + lane < ke) *ob = val;
                 ob += kWave;
                 kr += (double)kWave;
@@ -556,6 +563,8 @@ extern "C" int spline_solve_uniform_variant(const double* x, const double* y, in
             return launch_dense<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         case SOLVE_SPLINT_MUL:
             return launch_dense<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+        case SOLVE_HORNER:
+            return launch_dense<kHorner>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
         default:
             return SOLVE_E_ARG;
     }

@@ -1039,14 +1039,35 @@ __device__ void eval_uniform_range(const double* __restrict__ x, const double* _
 //               divisions by h and by 6 per query (splint_one__div);
 //   kSplintMul: the same with the division by 6 as a multiplication
 //               (splint_one__mul).
+//   kHorner:    not one of the paper's: the same cubic in the power basis of
+//               (q - a), its four coefficients formed once per interval and
+//               evaluated by Horner's rule (three FMAs per query).
 // (The paper's newint__vol variant is a C++ compiler-ordering trick with no
 // counterpart here.)
-enum NewintVariant : int { kHoisted = 0, kOrig = 1, kNoinv = 2, kSplintDiv = 3, kSplintMul = 4 };
+enum NewintVariant : int { kHoisted = 0, kOrig = 1, kNoinv = 2, kSplintDiv = 3, kSplintMul = 4, kHorner = 5 };
+
+// Power-basis coefficients of the cubic on [a, b] in t = q - a:
+// S = c0 + t (c1 + t (c2 + t c3)), from expanding newint's numerator with
+// b - q = (b - a) - t: c0 = u, c1 = (v - u)/(b - a) - (b - a)(v'' + 2u'')/6,
+// c2 = u''/2, c3 = (v'' - u'')/(6 (b - a)).
+struct Cubic4 {
+    double c0, c1, c2, c3;
+};
+__device__ __forceinline__ Cubic4 power_coeffs(double a, double b, double u, double v, double up, double vp,
+                                               double inv) {
+    const double ba = b - a;
+    return Cubic4{u, (v - u) * inv - ba * (vp + 2.0 * up) * (1.0 / 6.0), 0.5 * up, (vp - up) * inv * (1.0 / 6.0)};
+}
+__device__ __forceinline__ double horner(const Cubic4& c, double t) {
+    return fma(t, fma(t, fma(t, c.c3, c.c2), c.c1), c.c0);
+}
 
 template <int V>
 __device__ __forceinline__ double interp_variant(double q, double a, double b, double u, double v, double up,
                                                  double vp) {
-    if constexpr (V == kOrig || V == kNoinv) {
+    if constexpr (V == kHorner) {
+        return horner(power_coeffs(a, b, u, v, up, vp, 1.0 / (b - a)), q - a);
+    } else if constexpr (V == kOrig || V == kNoinv) {
         const double ba = b - a;
         const double xa = q - a;
         const double bx = b - q;
@@ -1164,6 +1185,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
             if (ks < ke) {
                 const double ba = bv - av;
                 const double ba2 = ba * ba;
+                Cubic4 cf{};
+                if constexpr (VARIANT == kHorner) cf = power_coeffs(av, bv, u, v, up, vp, inv);
                 // kr = k0 + lane + r is the query index k exactly (integers
                 // below 2^53 in double), so x0 + kr*h, one multiply then one
                 // add, is the position uniform_query(.., k) bit for bit (query
@@ -1180,7 +1203,13 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         q0 = x0 + s0;
                         q1 = x0 + s1;
                     }
-                    if constexpr (VARIANT != kHoisted) {
+                    if constexpr (VARIANT == kHorner) {
+                        ob[0] = horner(cf, q0 - av);
+                        ob[kWave] = horner(cf, q1 - av);
+                        ob += 2 * kWave;
+                        kr += (double)(2 * kWave);
+                        continue;
+                    } else if constexpr (VARIANT != kHoisted) {
                         ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
                         ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
                         ob += 2 * kWave;
@@ -1207,7 +1236,9 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         q = x0 + st;
                     }
                     double val;
-                    if constexpr (VARIANT != kHoisted) {
+                    if constexpr (VARIANT == kHorner) {
+                        val = horner(cf, q - av);
+                    } else if constexpr (VARIANT != kHoisted) {
                         val = interp_variant<VARIANT>(q, av, bv, u, v, up, vp);
                     } else {
                         const double xa = q - av, bx = bv - q;
