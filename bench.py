@@ -14,10 +14,13 @@ Workloads (--workload):
   small    1 curve, n = 13, m = 2048 (the worked size itself)
   plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
   batched  4096 curves, sizes log-uniform 0.1x..10x of the worked size, one
-           persistent fused launch (hipGraph replay), autotuned tiles
+           launch per step over autotuned work items (timed as a hipGraph
+           replay and as a direct launch; the faster gives the value)
   mixed    the batched workload with the FP32 solve + FP64 refinement
   served   Poisson arrivals at 2000 req/s (sizes 0.1x..100x) through the
            request API, continuous batching vs the plain one-request path
+  sweep    one curve per size, m = n, sizes 4 .. 2^28 from the paper's size
+           formula in shuffled order: solve and noop ns/point per size
 """
 from __future__ import annotations
 
@@ -119,6 +122,20 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     t1 = time.perf_counter()
     solve_ms = e_begin.elapsed_time(e_end) / K
     step_s = (t1 - t0) / K
+    # cold runs: a 1 GiB write before each launch evicts the inputs from the
+    # caches (the 256 MB last-level cache included); only the launch is timed
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold = []
+    for _ in range(10):
+        flush.fill_(1.0)
+        ec0 = torch.cuda.Event(enable_timing=True)
+        ec1 = torch.cuda.Event(enable_timing=True)
+        ec0.record(stream)
+        solve()
+        ec1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(ec0.elapsed_time(ec1))
+    del flush
     value = (n + m) / step_s
     # algorithmic bytes per launch of the fused kernel: read x, y (16 n),
     # write y'' (8 n) and write the m results (8 m); the halo rows each
@@ -138,6 +155,8 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, workload_name),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "kernels_ms": {dom: solve_ms, "two_launch_build": build_ms, "two_launch_eval_uniform": eval_ms},
+        "cold_ms": {"median": float(np.median(cold)), "max": float(np.max(cold)), "runs": len(cold),
+                    "note": "one launch after a 1 GiB write evicts the caches"},
         "points_per_s": m / step_s, "knots_per_s": n / step_s,
         "path_gbs": (24.0 * n + 8.0 * m) / step_s / 1e9,
     }
@@ -185,21 +204,42 @@ def bench_batched(args, precision):
     best, best_ms = api.spline_plan_autotune(plan, bufs, reps=5, cache_path=cache)
     stream = torch.cuda.Stream()
     api.spline_plan_capture(plan, bufs, stream=stream)
-    for _ in range(args.warmup):
-        api.spline_plan_replay(plan, stream=stream)
-    stream.synchronize()
     K = args.steps
-    e_begin = torch.cuda.Event(enable_timing=True)
-    e_end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e_begin.record(stream)
-    for k in range(K):
-        api.spline_plan_replay(plan, stream=stream)
-    e_end.record(stream)
-    stream.synchronize()
-    t1 = time.perf_counter()
-    launch_ms = e_begin.elapsed_time(e_end) / K  # one replay: every launch of the step
-    step_s = (t1 - t0) / K
+
+    def timed(step):
+        # K steps back to back on `stream`, one event pair around them (the
+        # average step without per-step event overhead) and the host clock
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        e_begin = torch.cuda.Event(enable_timing=True)
+        e_end = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e_begin.record(stream)
+        for k in range(K):
+            step()
+        e_end.record(stream)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        return e_begin.elapsed_time(e_end) / K, (t1 - t0) / K
+
+    # the step as a hipGraph replay, and as a direct launch of the plan
+    replay_ms, replay_s = timed(lambda: api.spline_plan_replay(plan, stream=stream))
+    direct_ms, direct_s = timed(lambda: api.spline_plan_run(plan, bufs, stream=stream))
+    step_s = min(replay_s, direct_s)
+    launch_ms = direct_ms  # the plan's kernels alone, launched back to back
+    # outputs rotated over >= 2 GiB, so that no launch finds its outputs in
+    # the 256 MB last-level cache
+    out_bytes = 8 * (int(b.qoff[-1]) + int(b.koff[-1]))
+    nrot = max(2, -(-(2 << 30) // out_bytes))
+    rot = [dict(bufs, yq=torch.empty_like(bufs["yq"]), ypp=torch.empty_like(bufs["ypp"])) for _ in range(nrot)]
+    it = [0]
+
+    def rotated():
+        api.spline_plan_run(plan, rot[it[0] % nrot], stream=stream)
+        it[0] += 1
+    rot_ms, _ = timed(rotated)
+    del rot
     N, M = int(b.koff[-1]), int(b.qoff[-1])
     value = (N + M) / step_s
     dbytes = 24.0 * N + 8.0 * M + 16.0 * b.count * 2 + 8.0 * b.count * 2
@@ -213,10 +253,15 @@ def bench_batched(args, precision):
                    "sizes": "log-uniform 0.1x..10x of (13, 2048)", "ends": "natural/flat/twist cycle", "seed": 0,
                    "tuning": {"block": best.block, "queries_per_tile": best.queries_per_tile,
                               "grid_per_cu": best.grid_per_cu, "fused": best.fused}},
-        "roofline": {"bound": "hbm", "kernel": "wave_items" if best.fused else "build+eval",
+        "roofline": {"bound": "hbm", "kernel": "coop_items" if best.fused == 3 else "wave_items",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("wave_items" if best.fused else "build+eval", wl),
+                     "traffic": measured_traffic("coop_items" if best.fused == 3 else "wave_items", wl),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": launch_ms},
+        "step_ms": {"graph_replay": replay_ms, "direct_launch": direct_ms,
+                    "host_graph_replay": replay_s * 1e3, "host_direct_launch": direct_s * 1e3,
+                    "direct_launch_outputs_rotated": rot_ms},
+        "rotated_outputs": {"buffers": nrot, "bytes": nrot * out_bytes, "avg_launch_ms": rot_ms,
+                            "frac": dbytes / (rot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if precision != api.FP64:
         # per-instance error of the mixed path against the FP64 oracle, in
@@ -298,6 +343,23 @@ def bench_served(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": None, "avg_launch_ms": None},
     }
+    # the paper's timing model (Gamma noise of mode Mo and sd sigma_inf +
+    # sigma_0/n around a per-point baseline) fitted to the latency samples,
+    # n = the request's knots + queries
+    from paper_2001_09253_amd import timing_model
+    tm = {}
+    for name, res in (("served", res_b), ("plain", res_p)):
+        try:
+            tm[name] = timing_model.fit(res.sizes, res.latency_s)
+        except Exception as e:  # a failed fit is reported, not fatal
+            tm[name] = {"error": repr(e)}
+    out["timing_model"] = tm
+    # admission under a tight HBM budget (32 MB holds about 20 of the largest
+    # requests), a shorter trace
+    tr32 = workloads.poisson_trace(4, args.rate, 3.5, 0.1, 100.0)
+    rq32 = serve.make_requests(tr32, 5)
+    r32, _ = serve.replay(tr32, rq32, warmup_s=0.5, budget=32 << 20, flags=api.NO_GRAPH)
+    out["budget_32mb"] = {"summary": r32.summary(), "stats": r32.stats}
     if args.sweep:
         rows = []
         for rate in (4000.0, 16000.0, 64000.0):
@@ -334,6 +396,95 @@ def bench_served(args):
     return out
 
 
+def bench_sweep(args):
+    """The paper-style size sweep on one curve (m = n): sizes from its formula
+    n = (r (sqrt(N) - sqrt(4)) + sqrt(4))^2 on a grid of r, N = 2^28, visited
+    in shuffled order; the one-launch solve and the noop kernel (generate and
+    bracket the queries only) per size, in ns per point.  Curves are prefixes
+    of one seeded draw of the paper's generator (a prefix is itself a draw)."""
+    import numpy as np
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    nmax = 1 << 28
+    sizes = np.unique(workloads.sweep_sizes(7, 48, nmax=nmax, nmin=4))
+    sizes = sizes[sizes >= 4]
+    rng = np.random.default_rng(7)
+    rng.shuffle(sizes)
+    x, y = workloads.paper_curve(np.random.default_rng(0), nmax)
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    del x, y
+    ypp = torch.empty(nmax, dtype=torch.float64, device=dev)
+    out = torch.empty(nmax, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in sizes:
+        n = int(n)
+        m = n
+        xs, ys = xd[:n], yd[:n]
+
+        def solve():
+            api.spline_solve_uniform(xs, ys, 1e32, 1e32, m, out[:m], ypp[:n])
+
+        def noop():
+            api.spline_noop_uniform(xs, m, out[:m])
+        res = {}
+        for name, fn in (("solve", solve), ("noop", noop)):
+            fn()
+            torch.cuda.synchronize()
+            reps = int(min(200, max(3, 2e8 // (n + 1))))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps
+        b_alg = 24.0 * n + 8.0 * m
+        rows.append({"n": n, "m": m, "solve_us": res["solve"] * 1e3, "noop_us": res["noop"] * 1e3,
+                     "solve_ns_per_point": res["solve"] * 1e6 / m, "noop_ns_per_point": res["noop"] * 1e6 / m,
+                     "solve_gbs": b_alg / (res["solve"] * 1e-3) / 1e9})
+    rows.sort(key=lambda r: r["n"])
+    big = rows[-1]
+    out_d = {
+        "metric": METRIC, "value": (big["n"] + big["m"]) / (big["solve_us"] * 1e-6), "unit": UNIT, "n_gpus": 1,
+        "steps": len(rows), "warmup": 1, "ms_per_step": big["solve_us"] * 1e-3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sweep: 1 curve per size, m = n, %d sizes from 4 to 2^28 (the paper's size formula), "
+                               "shuffled" % len(rows), "seed": 0},
+        "roofline": {"bound": "hbm", "kernel": "solve_uniform", "achieved": big["solve_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": big["solve_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": 24.0 * big["n"] + 8.0 * big["m"],
+                     "avg_launch_ms": big["solve_us"] * 1e-3},
+        "sweep": rows,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle single-threaded, as in the paper, at the sweep's sizes up
+        # to 2^20 (bounded by --cpu-seconds overall)
+        xh, yh = workloads.paper_curve(np.random.default_rng(0), 1 << 20)
+        cpu = []
+        t_all = oracle.now()
+        for r in rows:
+            n = r["n"]
+            if n > (1 << 20) or oracle.now() - t_all > args.cpu_seconds:
+                continue
+            reps = 0
+            t0 = oracle.now()
+            while True:
+                oracle.spline_uniform(xh[:n], yh[:n], 1e32, 1e32, n)
+                reps += 1
+                if oracle.now() - t0 > 0.05:
+                    break
+            cpu.append({"n": n, "ns_per_point": (oracle.now() - t0) / reps / n * 1e9})
+        out_d["cpu_baseline"] = {"value": None, "unit": "ns/point", "cores": 1, "kind": "oracle",
+                                 "sample": "single thread, m = n, sizes of the sweep up to 2^20", "points": cpu}
+    return out_d
+
+
 def bench_copy(args):
     """Calibration only: a plain device-to-device copy of 256 MiB (reads and
     writes 256 MiB per launch), the reference the HBM traffic counters of the
@@ -365,7 +516,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy"])
+                    choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy", "sweep"])
     ap.add_argument("--variant", default=None,
                     choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul", "horner"],
                     help="single-curve workloads: time this evaluation formula on the one-launch kernel")
@@ -392,6 +543,8 @@ def main():
         out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)
     elif args.workload == "copy":
         out = bench_copy(args)
+    elif args.workload == "sweep":
+        out = bench_sweep(args)
     else:
         out = bench_served(args)
     print(json.dumps(out))

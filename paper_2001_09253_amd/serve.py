@@ -44,6 +44,7 @@ class ReplayResult:
     requests: int
     errors: int
     stats: dict = field(default_factory=dict)
+    sizes: np.ndarray = field(default_factory=lambda: np.zeros(0))  # per measured request, n + m
 
     def summary(self) -> dict:
         lat = self.latency_s * 1e3
@@ -159,5 +160,6 @@ def replay(trace: workloads.Trace, reqs: list[Request], *, plain: bool = False, 
     steps = int(sum(reqs[r].n + reqs[r].m for r in np.nonzero(sel)[0]))
     window = float(done_t[sel].max() - arrive[sel].min()) if sel.any() else 0.0
     errors = int(np.sum(status[sel] != api.DONE))
-    res = ReplayResult(lat, lag, steps, window, int(sel.sum()), errors, stats)
+    sizes = np.array([reqs[r].n + reqs[r].m for r in np.nonzero(sel)[0]], dtype=np.float64)
+    res = ReplayResult(lat, lag, steps, window, int(sel.sum()), errors, stats, sizes)
     return res, outputs
