@@ -209,7 +209,7 @@ def test_eval_points_matches_oracle(kind):
 
 SOLVE_CASES = [(3, 5), (13, 2048), (100, 7), (513, 100000), (1024, 1), (1025, 4096), (4097, 333),
                (13000, 2048000), (20000, 20000), (65536, 1 << 20), (300000, 1000), (250, 3000000),
-               (300001, 19200000)]
+               (300001, 19200000), (1 << 20, 1 << 16), (70001, 3), (100000, 800000)]
 
 
 @pytest.mark.parametrize("n,m", SOLVE_CASES)
@@ -262,6 +262,39 @@ def test_solve_uniform_adaptive_halo_adversarial_spacing(kind, bc):
         assert int(host(st)[0]) == api.OK
         assert_close(host(ypp), o_ypp, "%s ypp m=%d %s" % (kind, m, name))
         assert_close(host(yq), o_yq, "%s yq m=%d %s" % (kind, m, name))
+
+
+@pytest.mark.parametrize("kind", ["alternating", "sawtooth_down", "loguniform", "clustered"])
+def test_solve_uniform_sparse_long_curves(kind):
+    # long curves with far fewer queries than intervals take the kernel that
+    # solves blocks of 255 intervals; the alternating widths force its uniform
+    # fallback halo (the widest span it holds)
+    n, m = 70000, 3000
+    rng = np.random.default_rng(41)
+    if kind == "alternating":
+        x, y = w.alternating_curve(rng, n, scale=10.0)
+    else:
+        x, y = w.spacing_curve(rng, n, kind)
+    for sd, ed in ((1e32, 1e32), (-1.0, 2.0)):
+        xd, yd = dev(x), dev(y)
+        ypp = torch.full_like(xd, np.nan)
+        yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
+        st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        api.spline_solve_uniform(xd, yd, sd, ed, m, yq, ypp, st)
+        o_yq, o_ypp = oracle.spline_uniform(x, y, sd, ed, m)
+        assert int(host(st)[0]) == api.OK
+        assert_close(host(ypp), o_ypp, "%s sparse ypp" % kind)
+        assert_close(host(yq), o_yq, "%s sparse yq" % kind)
+
+
+def test_solve_uniform_sparse_bad_knots():
+    x, y = w.paper_curve(np.random.default_rng(43), 100000)
+    x[77777] = x[77776]
+    xd, yd = dev(x), dev(y)
+    yq = torch.empty(1000, dtype=torch.float64, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    api.spline_solve_uniform(xd, yd, 0.0, 0.0, 1000, yq, None, st)
+    assert int(host(st)[0]) == api.E_ORDER
 
 
 def test_solve_uniform_bad_knots_and_reuse():
