@@ -12,10 +12,11 @@
 // by a_j / (b_j - a_j c'_{j-1}) < 2/3 (since 0 <= c' <= 1/2), and in the back
 // substitution a perturbation of y''_{j+1} reaches y''_j multiplied by
 // |c'_j| <= 1/2.  A uniform halo of 128 rows therefore changes the block's y''
-// by less than 1e-21 max|y''|; the dense kernel below takes each block's
-// halo from the knots themselves (adaptive_halo), shortest that keeps the
-// same kind of bound under 2^-60 max|y''|.  Curves shorter than the block
-// plus both halos are solved whole, exactly.
+// by less than 1e-21 max|y''|; every kernel below takes each block's halo
+// from the knots themselves (adaptive_halo), shortest that keeps the same
+// kind of bound under 2^-60 max|y''|, and falls back to the uniform 128 rows
+// when 63 do not suffice.  Curves shorter than the block plus both halos are
+// solved whole, exactly.
 //
 // Dense curves (many queries per interval) take either a workgroup of four
 // wavefronts per block (one solves, all evaluate) or one wavefront per block
@@ -37,6 +38,7 @@ namespace spl {
 
 constexpr int kSolveBlock = 256;
 constexpr int kHalo = 128;
+constexpr double kHaloEps = 0x1p-60;  // adaptive halos: dropped coupling below 2^-60 max|y''|
 
 template <int BK>
 struct BlockSolve {
@@ -62,6 +64,7 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
     __shared__ int64_t kq[BK + 1];   // first query of each interval, then the block's end
     __shared__ Fwd lds_f[kSolveBlock / kWave];
     __shared__ Bwd lds_b[kSolveBlock / kWave];
+    __shared__ int span[2];
     const int tid = threadIdx.x;
     const int ni = (int)n;
     const double x0 = x[0];
@@ -70,8 +73,18 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
     for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
         const int j0 = (int)(blk * BK);
         const int j1 = min(j0 + BK, ni - 1);  // intervals [j0, j1)
-        const int rs = max(0, j0 - kHalo);
-        const int re = min(ni, j1 + 1 + kHalo);
+        // the halos from the knots (adaptive_halo's two sides, one wavefront
+        // each), at most the uniform kHalo rows
+        if (tid < kWave) {
+            const int r = halo_start(x, j0, kHaloEps, kHalo, tid);
+            if (tid == 0) span[0] = r;
+        } else if (tid < 2 * kWave) {
+            const int r = halo_end(x, ni, j1, kHaloEps, kHalo, tid - kWave);
+            if (tid == kWave) span[1] = r;
+        }
+        __syncthreads();
+        const int rs = span[0];
+        const int re = span[1];
         const bool bad = build_span<kSolveBlock, B::kChunk, false, SoloGroup, false>(
             x, y, ni, rs, re, sd, ed, nullptr, nullptr, sx, lds_f, lds_b, SoloGroup{}, tid, sy, so);
         if (bad && status && tid == 0) atomicMin(status, kStatusOrder);
@@ -130,7 +143,6 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
 constexpr int kWaveSpanCH = 5;           // 320 rows >= kMaxWaveBK + 1 + 2 * kHalo
 constexpr int kMaxWaveBK = 32;
 constexpr int kWavesPerGroup = 4;
-constexpr double kHaloEps = 0x1p-60;
 
 struct WaveSolveSmem {
     double sx[kWave * kWaveSpanCH + 2];
