@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the committed measurement record.
 
     python -m paper_2001_09253_amd.profiling stats <rocprofv3 dir> <out.txt> <command...>
-        writes the per-kernel duration table of a --kernel-trace --stats run,
-        headed by the command that produced it;
+        writes the per-kernel duration table of a --kernel-trace --stats run
+        (average, and the median dispatch from the trace), headed by the
+        command that produced it and $PROFILE_NOTE, if set;
     python -m paper_2001_09253_amd.profiling traffic <kernel> <workload> <fetch dir> <write dir>
         <copy fetch dir> <copy write dir> <copy bytes> [<kernel substring>]
         scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over the
@@ -57,15 +58,37 @@ def _kernel_rows(prof_dir):
             for r in con.execute(q)]
 
 
-def stats(prof_dir, out_path, command):
+def _medians(prof_dir):
+    """Median dispatch duration (ns) per kernel from the run's kernel trace,
+    if the trace is there."""
+    hits = glob.glob(os.path.join(prof_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not hits:
+        return {}
+    per = {}
+    with open(hits[0]) as f:
+        for r in csv.DictReader(f):
+            per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = {}
+    for k, v in per.items():
+        v.sort()
+        out[k] = v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+    return out
+
+
+def stats(prof_dir, out_path, command, note=None):
     rows = _kernel_rows(prof_dir)
+    med = _medians(prof_dir)
     lines = ["# rocprofv3 --kernel-trace --stats", "# command: " + command,
-             "# kernel sources: " + kernel_source_hash(), "",
-             "%-72s %7s %12s %12s %12s" % ("kernel", "calls", "avg_us", "min_us", "max_us")]
+             "# kernel sources: " + kernel_source_hash()]
+    if note:
+        lines += ["# " + line for line in note.splitlines()]
+    lines += ["", "%-72s %7s %12s %12s %12s %12s" % ("kernel", "calls", "avg_us", "median_us", "min_us", "max_us")]
     for r in rows:
         name = r["Name"] if len(r["Name"]) <= 72 else r["Name"][:69] + "..."
-        lines.append("%-72s %7s %12.3f %12.3f %12.3f" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
-                                                      float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+        m = med.get(r["Name"])
+        lines.append("%-72s %7s %12.3f %12s %12.3f %12.3f" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                           "%.3f" % (m / 1e3) if m is not None else "-",
+                                                           float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -111,7 +134,7 @@ def traffic(kernel, workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy
 
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), os.environ.get("PROFILE_NOTE"))
     elif len(sys.argv) >= 9 and sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     else:
