@@ -311,8 +311,13 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
                            lane);
 }
 
+// (at least 5 wavefronts per SIMD up to 3 rows per lane: the register
+// budget this asks for, 96, holds those instantiations without spills and
+// lets the 4096-curve batch's items all start in the first round; wider
+// spans are LDS-bound anyway)
 template <int CH, int WPG, bool BUILD, bool MIXED>
-__global__ __launch_bounds__(WPG * kWave) void wave_items_kernel(BatchDevArgs a) {
+__global__ __launch_bounds__(WPG * kWave) __attribute__((amdgpu_waves_per_eu(CH <= 3 ? 5 : 1, 8))) void
+wave_items_kernel(BatchDevArgs a) {
     __shared__ WaveSmem<CH> smem[WPG];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
