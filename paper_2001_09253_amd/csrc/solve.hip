@@ -298,118 +298,6 @@ struct CoopSmem {
     int rs, re;
 };
 
-// Queries k0 .. k1-1 of the block [j0, j1) (all inside it), by one
-// wavefront, with the block's knots, values and y'' in LDS and kq as above.
-// Query k lies in interval t exactly when kq[t - j0] <= k < kq[t + 1 - j0].
-template <int VARIANT>
-__device__ __forceinline__ void coop_eval(const CoopSmem& sm, int lo, int rs, int j0, int j1, double x0, double xl,
-                                          double h, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out,
-                                          int lane) {
-    const int nbk = j1 - j0;
-    int ca = 0, cb = 0;
-    {
-        const int i = 1 + lane;  // interior knots of the block (nbk <= kMaxWaveBK < kWave)
-        const bool in = i < nbk;
-        const int64_t v = in ? sm.kq[i] : 0;
-        ca = __popcll(__ballot(in && v <= k0));
-        cb = __popcll(__ballot(in && v <= k1 - 1));
-    }
-    const int t0 = j0 + ca;
-    const int t1 = j0 + cb;
-    const int nt = t1 - t0 + 1;
-    const double* sx = sm.sx;
-    const double* sy = sm.sy;
-    const double* so = sm.so;
-    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
-        const double kl0 = (double)k0 + (double)lane;
-        double* __restrict__ o = out + k0 + lane;
-        for (int t = t0; t <= t1; ++t) {
-            const int64_t ka = (t == t0) ? k0 : sm.kq[t - j0];
-            const int64_t kb = (t == t1) ? k1 : sm.kq[t + 1 - j0];
-            if (ka >= kb) continue;
-            const double av = sx[t - lo], bv = sx[t + 1 - lo];
-            const double u = sy[t - lo], v = sy[t + 1 - lo];
-            const double up = so[t - rs], vp = so[t + 1 - rs];
-            const double inv = sm.inv[t - j0];
-            const double ba = bv - av;
-            const double ba2 = ba * ba;
-            Cubic4 cf{};
-            if constexpr (VARIANT == kHorner) cf = power_coeffs(av, bv, u, v, up, vp, inv);
-            const int ks = __builtin_amdgcn_readfirstlane((int)(ka - k0));  // uniform: loop bounds in SGPRs
-            const int ke = __builtin_amdgcn_readfirstlane((int)(kb - k0));
-            // kr = k0 + lane + r is the query index k exactly, so x0 + kr*h
-            // (one multiply, then one add) is uniform_query(.., k) bit for bit;
-            // query m-1 (x[n-1] itself) is patched below
-            double kr = kl0 + (double)ks;
-            double* __restrict__ ob = o + ks;
-            int r = ks;
-            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
-                double q0, q1;
-                {
-#pragma clang fp contract(off)
-                    const double s0 = kr * h;
-                    const double s1 = (kr + (double)kWave) * h;
-                    q0 = x0 + s0;
-                    q1 = x0 + s1;
-                }
-                if constexpr (VARIANT == kHoisted) {
-                    // a6: newint with the interval's 1/(b - a) and (b - a)^2
-                    const double xa0 = q0 - av, bx0 = bv - q0;
-                    const double xa1 = q1 - av, bx1 = bv - q1;
-                    const double l0 = xa0 * v + bx0 * u;
-                    const double l1 = xa1 * v + bx1 * u;
-                    const double c0 = (xa0 * xa0 - ba2) * xa0 * vp + (bx0 * bx0 - ba2) * bx0 * up;
-                    const double c1 = (xa1 * xa1 - ba2) * xa1 * vp + (bx1 * bx1 - ba2) * bx1 * up;
-                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
-                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
-                } else if constexpr (VARIANT == kHorner) {
-                    ob[0] = horner(cf, q0 - av);
-                    ob[kWave] = horner(cf, q1 - av);
-                } else {
-                    ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
-                    ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
-                }
-                ob += 2 * kWave;
-                kr += (double)(2 * kWave);
-            }
-            for (; r < ke; r += kWave) {
-                double q;
-                {
-#pragma clang fp contract(off)
-                    const double st = kr * h;
-                    q = x0 + st;
-                }
-                double val;
-                if constexpr (VARIANT == kHorner) val = horner(cf, q - av);
-                else val = interp_one<VARIANT>(q, av, bv, u, v, up, vp, inv);
-                if (r + lane < ke) *ob = val;
-                ob += kWave;
-                kr += (double)kWave;
-            }
-        }
-        if (k1 == m && m > 1 && lane == 0) {
-            const int t = t1;  // query m-1 is x[n-1] itself, in the last interval
-            out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
-                                             so[t - rs], so[t + 1 - rs], sm.inv[t - j0]);
-        }
-        return;
-    }
-    // fewer queries per interval: 64 consecutive queries at a time, each lane
-    // walking from the wavefront's current interval
-    int t = t0;
-    for (int64_t kc = k0; kc < k1; kc += kWave) {
-        const int64_t k = kc + lane;
-        const bool live = k < k1;
-        const double q = uniform_query(x0, xl, h, m, live ? k : k1 - 1);
-        int tl = t;
-        while (tl + 1 <= t1 && sm.kq[tl + 1 - j0] <= (live ? k : k1 - 1)) ++tl;
-        t = __shfl(tl, kWave - 1);
-        if (live)
-            out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
-                                         so[tl - rs], so[tl + 1 - rs], sm.inv[tl - j0]);
-    }
-}
-
 template <int VARIANT>
 __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
@@ -507,7 +395,7 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const int64_t k0 = ka + per * p + min(p, rem);
     const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
     if (k0 >= k1) return;
-    coop_eval<VARIANT>(sm, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq, lane);
+    eval_block_kq<false, VARIANT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq, lane);
 }
 
 static int cu_count() {

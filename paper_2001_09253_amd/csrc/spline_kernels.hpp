@@ -1295,6 +1295,126 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
     }
 }
 
+// Queries k0 .. k1-1 of the block [j0, j1) (all inside it), by one
+// wavefront, with the block's knots and values staged at [j - lo], its y'' at
+// [i - rs], sinv[t - j0] = 1/(x_{t+1} - x_t), and kq[i] the first query above
+// knot j0 + i (kq[0] and kq[j1 - j0] the block's first query and end): query
+// k lies in interval t exactly when kq[t - j0] <= k < kq[t + 1 - j0], so the
+// intervals come from integer compares alone.  Many queries per interval:
+// interval by interval, its constants in registers, 64 queries per store,
+// two independent rows per iteration, loop bounds in scalar registers.  Few:
+// 64 consecutive queries at a time, each lane stepping from the wavefront's
+// current interval.  Query m-1 (x[n-1] itself) is patched at the end.
+template <bool MIXED, int VARIANT = kHoisted>
+__device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy, const double* so,
+                                              const double* sinv, const int64_t* kq, int lo, int rs, int j0, int j1,
+                                              double x0, double xl, double h, int64_t m, int64_t k0, int64_t k1,
+                                              double* __restrict__ out, int lane) {
+    const int nbk = j1 - j0;
+    int ca = 0, cb = 0;
+    for (int i = 1 + lane; i - lane < nbk; i += kWave) {  // interior knots of the block
+        const bool in = i < nbk;
+        const int64_t v = in ? kq[i] : 0;
+        ca += __popcll(__ballot(in && v <= k0));
+        cb += __popcll(__ballot(in && v <= k1 - 1));
+    }
+    const int t0 = j0 + ca;
+    const int t1 = j0 + cb;
+    const int nt = t1 - t0 + 1;
+    if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
+        const double kl0 = (double)k0 + (double)lane;
+        double* __restrict__ o = out + k0 + lane;
+        for (int t = t0; t <= t1; ++t) {
+            const int64_t ka = (t == t0) ? k0 : kq[t - j0];
+            const int64_t kb = (t == t1) ? k1 : kq[t + 1 - j0];
+            if (ka >= kb) continue;
+            const double av = sx[t - lo], bv = sx[t + 1 - lo];
+            const double u = sy[t - lo], v = sy[t + 1 - lo];
+            const double up = so[t - rs], vp = so[t + 1 - rs];
+            const double inv = sinv[t - j0];
+            const double ba = bv - av;
+            const double ba2 = ba * ba;
+            Cubic4 cf{};
+            if constexpr (VARIANT == kHorner) cf = power_coeffs(av, bv, u, v, up, vp, inv);
+            const int ks = __builtin_amdgcn_readfirstlane((int)(ka - k0));  // uniform: loop bounds in SGPRs
+            const int ke = __builtin_amdgcn_readfirstlane((int)(kb - k0));
+            // kr = k0 + lane + r is the query index k exactly, so x0 + kr*h
+            // (one multiply, then one add) is uniform_query(.., k) bit for bit
+            double kr = kl0 + (double)ks;
+            double* __restrict__ ob = o + ks;
+            int r = ks;
+            for (; r + 2 * kWave <= ke; r += 2 * kWave) {
+                double q0, q1;
+                {
+#pragma clang fp contract(off)
+                    const double s0 = kr * h;
+                    const double s1 = (kr + (double)kWave) * h;
+                    q0 = x0 + s0;
+                    q1 = x0 + s1;
+                }
+                if constexpr (VARIANT == kHoisted) {
+                    // a6: newint with the interval's 1/(b - a) and (b - a)^2
+                    const double xa0 = q0 - av, bx0 = bv - q0;
+                    const double xa1 = q1 - av, bx1 = bv - q1;
+                    const double l0 = xa0 * v + bx0 * u;
+                    const double l1 = xa1 * v + bx1 * u;
+                    const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
+                    const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
+                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
+                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                } else if constexpr (VARIANT == kHorner) {
+                    ob[0] = horner(cf, q0 - av);
+                    ob[kWave] = horner(cf, q1 - av);
+                } else {
+                    ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
+                    ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
+                }
+                ob += 2 * kWave;
+                kr += (double)(2 * kWave);
+            }
+            for (; r < ke; r += kWave) {
+                double q;
+                {
+#pragma clang fp contract(off)
+                    const double st = kr * h;
+                    q = x0 + st;
+                }
+                double val;
+                if constexpr (VARIANT == kHoisted) {
+                    const double xa = q - av, bx = bv - q;
+                    val = (xa * v + bx * u + (1.0 / 6.0) * cubic_term<MIXED>(xa, bx, ba2, up, vp)) * inv;
+                } else if constexpr (VARIANT == kHorner) {
+                    val = horner(cf, q - av);
+                } else {
+                    val = interp_variant<VARIANT>(q, av, bv, u, v, up, vp);
+                }
+                if (r + lane < ke) *ob = val;
+                ob += kWave;
+                kr += (double)kWave;
+            }
+        }
+    } else {
+        int t = t0;
+        for (int64_t kc = k0; kc < k1; kc += kWave) {
+            const int64_t k = kc + lane;
+            const bool live = k < k1;
+            const int64_t kk = live ? k : k1 - 1;
+            const double q = uniform_query(x0, xl, h, m, kk);
+            int tl = t;
+            while (tl + 1 <= t1 && kq[tl + 1 - j0] <= kk) ++tl;
+            t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
+            if (live)
+                out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
+                                             so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
+        }
+    }
+    if (k1 == m && m > 1 && lane == 0) {
+        const int t = t1;  // query m-1 is x[n-1] itself, in the last interval
+        out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo], so[t - rs],
+                                         so[t + 1 - rs], sinv[t - j0]);
+    }
+}
+
 // A tile of BLOCK*QPT consecutive uniform queries starting at k0.
 template <int BLOCK, int QPT, int WIN, int MODE, bool NT_STORE>
 __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __restrict__ y,
