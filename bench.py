@@ -97,14 +97,17 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     # the timed path: one launch per step (build and evaluate fused); with
     # --variant, the one-launch kernel with one of the paper's evaluation
     # formulas
+    # (the launch stream is passed explicitly: looking up torch's current
+    # stream on every call costs host time the smallest workload would see)
+    sp = stream.cuda_stream
     if args.variant is None:
         def solve():
-            api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp)
+            api.spline_solve_uniform(x, y, sd, ed, m, yq, ypp, stream=sp)
     else:
         code = api.VARIANTS[args.variant]
 
         def solve():
-            api.spline_solve_uniform_variant(x, y, sd, ed, m, code, yq, ypp)
+            api.spline_solve_uniform_variant(x, y, sd, ed, m, code, yq, ypp, stream=sp)
     for _ in range(args.warmup):
         solve()
     torch.cuda.synchronize()
