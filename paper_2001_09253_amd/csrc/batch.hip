@@ -588,10 +588,19 @@ void Batch::make_tables() {
             }
         }
     }
-    // decreasing work, so that the last wavefronts to start hold the least
+    // decreasing work, so that the last wavefronts to start hold the least,
+    // dealt out in stripes of one item per wavefront of a dispatch round
+    // (workgroup k lands on compute unit k mod #CU) with every other stripe
+    // reversed, so that the compute units' shares of work come out even
     std::vector<size_t> order(witems_.size());
     std::iota(order.begin(), order.end(), (size_t)0);
     std::stable_sort(order.begin(), order.end(), [&](size_t p, size_t q) { return cost[p] > cost[q]; });
+    const size_t per_group = tuning_.fused == 3 ? 1 : (size_t)(tuning_.block / kWave);
+    const size_t groups = (size_t)std::max(1, num_cu_) *
+                          (tuning_.fused != 3 && tuning_.grid_per_cu > 0 ? (size_t)tuning_.grid_per_cu : 1);
+    const size_t stripe = groups * per_group;
+    for (size_t s0 = stripe; s0 < order.size(); s0 += 2 * stripe)
+        std::reverse(order.begin() + s0, order.begin() + std::min(order.size(), s0 + stripe));
     std::vector<WaveItem> sorted(witems_.size());
     for (size_t k = 0; k < order.size(); ++k) sorted[k] = witems_[order[k]];
     witems_.swap(sorted);
