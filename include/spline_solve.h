@@ -176,12 +176,14 @@ int spline_eval_uniform(const double *x, const double *y, const double *ypp, int
                         int64_t m, double *yq, void *stream);
 
 /* Steps a1-a6 for one curve in a single launch, with no synchronisation
- * between workgroups: each workgroup owns a block of knot intervals, solves
- * the paper's rows over that block plus 128 rows on either side (coupling
- * beyond them dropped; by the diagonal dominance the paper proves, this
- * changes y'' by less than 1e-21 max|y''|, and curves of up to 2*128 + 1
- * rows more than a block are solved whole), then evaluates the uniform
- * queries that fall in its intervals.
+ * between workgroups: each workgroup (or wavefront) owns a block of knot
+ * intervals, solves the paper's rows over that block plus a halo of rows on
+ * either side and evaluates the uniform queries that fall in its intervals.
+ * The halo is sized from the knots: the shortest (up to 63 rows) for which
+ * the dropped coupling, bounded through the paper's recurrences, is below
+ * 2^-60 max|y''|, else 128 rows (below 1e-21 max|y''| by the diagonal
+ * dominance the paper proves); curves shorter than a block plus both halos
+ * are solved whole.  The kernel is chosen by the query density m/(n-1).
  * x, y: n device doubles; yq: m device doubles (output); ypp: nullable, n
  * device doubles (output).  status: nullable device int32 that the call
  * leaves unchanged unless it finds unordered knots, in which case it is set
