@@ -152,7 +152,7 @@ struct WaveSolveSmem {
     int32_t bq[kMaxWaveBK + 1];
 };
 
-template <int VARIANT>
+template <int VARIANT, bool WT>
 __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
     double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nblocks, int bk,
@@ -205,8 +205,8 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     if (k0 >= k1) return;
     // (few wavefronts per SIMD here: the next interval's constants are read
     // while the current one is evaluated)
-    wave_eval_block<false, true, VARIANT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0,
-                                          k1, yq, lane);
+    wave_eval_block<false, true, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m,
+                                              k0, k1, yq, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -228,7 +228,7 @@ struct SparseSmem {
     int32_t bq[kSparseBK + 1];
 };
 
-template <int VARIANT>
+template <int VARIANT, bool WT>
 __global__ __launch_bounds__(kWave) void solve_sparse_kernel(const double* __restrict__ x,
                                                              const double* __restrict__ y, int64_t n64, double sd,
                                                              double ed, int64_t m, double* __restrict__ yq,
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(kWave) void solve_sparse_kernel(const double* __res
     const int64_t kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, sm.sx[j1 - lo]);
     wave_sync();
     if (ka >= kb) return;
-    wave_eval_block<false, false, VARIANT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, ka,
-                                           kb, yq, lane);
+    wave_eval_block<false, false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh,
+                                               m, ka, kb, yq, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,7 +298,7 @@ struct CoopSmem {
     int rs, re;
 };
 
-template <int VARIANT>
+template <int VARIANT, bool WT>
 __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
     double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int bk, int shares) {
@@ -395,7 +395,8 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const int64_t k0 = ka + per * p + min(p, rem);
     const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
     if (k0 >= k1) return;
-    eval_block_kq<false, VARIANT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq, lane);
+    eval_block_kq<false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq,
+                                      lane);
 }
 
 static int cu_count() {
@@ -434,6 +435,13 @@ static int launch_blocks(const double* x, const double* y, int64_t n, double sd,
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
+// Results written through (agent-scope stores) while they fit well inside
+// the 256 MB last-level cache: the kernel then ends without writing back
+// dirty L2 lines (about 1.5 us of a 10 us launch at 16 MB); past it the
+// default write-back stores stream faster (measured: faster up to 256 MB of
+// results, twice as slow at 512 MB).
+static bool write_through(int64_t m) { return m <= ((int64_t)1 << 24); }
+
 // Block size from the query density: small blocks when a block's queries
 // alone keep a workgroup busy, larger ones when queries are sparse and the
 // halo rows would dominate.
@@ -450,8 +458,12 @@ static int launch_waves_solve(const double* x, const double* y, int64_t n, doubl
     const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / 2730.0)));
     const int64_t groups = (nblocks * shares + kWavesPerGroup - 1) / kWavesPerGroup;
     if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
-    solve_waves_kernel<VARIANT><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
-                                                                                  status, nblocks, bk, shares);
+    if (write_through(m))
+        solve_waves_kernel<VARIANT, true><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(
+            x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk, shares);
+    else
+        solve_waves_kernel<VARIANT, false><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(
+            x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk, shares);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
@@ -471,8 +483,12 @@ static int launch_coop_solve(const double* x, const double* y, int64_t n, double
     const double per_block = queries_per_knot * bk;
     const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / share_q)));
     if (nblocks * shares > 0x7fffffffLL) return SOLVE_E_SIZE;
-    solve_coop_kernel<VARIANT><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
-                                                                                    status, bk, shares);
+    if (write_through(m))
+        solve_coop_kernel<VARIANT, true><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(
+            x, y, n, sd, ed, m, yq, ypp, status, bk, shares);
+    else
+        solve_coop_kernel<VARIANT, false><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(
+            x, y, n, sd, ed, m, yq, ypp, status, bk, shares);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
@@ -482,7 +498,10 @@ static int launch_sparse_solve(const double* x, const double* y, int64_t n, doub
     bk = std::max(1, std::min(bk, kSparseBK));
     const int64_t nblocks = (n - 1 + bk - 1) / bk;
     if (nblocks > 0x7fffffffLL) return SOLVE_E_SIZE;
-    solve_sparse_kernel<VARIANT><<<(unsigned)nblocks, kWave, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk);
+    if (write_through(m))
+        solve_sparse_kernel<VARIANT, true><<<(unsigned)nblocks, kWave, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk);
+    else
+        solve_sparse_kernel<VARIANT, false><<<(unsigned)nblocks, kWave, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 

@@ -1120,7 +1120,17 @@ __device__ __forceinline__ double cubic_term(double xa, double bx, double ba2, d
     }
 }
 
-template <bool MIXED, bool PREFETCH = false, int VARIANT = kHoisted>
+// A result store.  WT: an agent-scope store, written through to memory, so
+// that no dirty result lines are left in the XCDs' L2 caches for the kernel's
+// end to write back (which pays on outputs that fit the last-level cache;
+// larger ones stream faster through the default write-back stores).
+template <bool WT>
+__device__ __forceinline__ void put_out(double* p, double v) {
+    if constexpr (WT) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+template <bool MIXED, bool PREFETCH = false, int VARIANT = kHoisted, bool WT = false>
 __device__ void wave_eval_block(const double* sx, const double* sy, const double* so, const double* sinv,
                                 int32_t* bq, int lo, int rs, int j0, int j1, double x0, double xl, double h,
                                 double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane) {
@@ -1204,14 +1214,14 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         q1 = x0 + s1;
                     }
                     if constexpr (VARIANT == kHorner) {
-                        ob[0] = horner(cf, q0 - av);
-                        ob[kWave] = horner(cf, q1 - av);
+                        put_out<WT>(ob, horner(cf, q0 - av));
+                        put_out<WT>(ob + kWave, horner(cf, q1 - av));
                         ob += 2 * kWave;
                         kr += (double)(2 * kWave);
                         continue;
                     } else if constexpr (VARIANT != kHoisted) {
-                        ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
-                        ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
+                        put_out<WT>(ob, interp_variant<VARIANT>(q0, av, bv, u, v, up, vp));
+                        put_out<WT>(ob + kWave, interp_variant<VARIANT>(q1, av, bv, u, v, up, vp));
                         ob += 2 * kWave;
                         kr += (double)(2 * kWave);
                         continue;
@@ -1223,8 +1233,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                     const double l1 = xa1 * v + bx1 * u;
                     const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
                     const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
-                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
-                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                    put_out<WT>(ob, (l0 + (1.0 / 6.0) * c0) * inv);
+                    put_out<WT>(ob + kWave, (l1 + (1.0 / 6.0) * c1) * inv);
                     ob += 2 * kWave;
                     kr += (double)(2 * kWave);
                 }
@@ -1246,7 +1256,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
                         val = (l + (1.0 / 6.0) * cc) * inv;
                     }
-                    if (r + lane < ke) *ob = val;
+                    if (r + lane < ke) put_out<WT>(ob, val);
                     ob += kWave;
                     kr += (double)kWave;
                 }
@@ -1272,8 +1282,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         if (k1 == m && m > 1 && lane == 0) {
             // query m-1 is x[n-1] itself (for m > 1), in interval t1
             const int t = t1;
-            out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
-                                             so[t - rs], so[t + 1 - rs], sinv[t - j0]);
+            put_out<WT>(out + (m - 1), interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo],
+                                                           sy[t + 1 - lo], so[t - rs], so[t + 1 - rs], sinv[t - j0]));
         }
         return;
     }
@@ -1289,8 +1299,8 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         while (tl + 1 <= t1 && sx[tl + 1 - lo] < q) ++tl;
         t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
         if (live) {
-            out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
-                                         so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
+            put_out<WT>(out + k, interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
+                                                     so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]));
         }
     }
 }
@@ -1305,7 +1315,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
 // two independent rows per iteration, loop bounds in scalar registers.  Few:
 // 64 consecutive queries at a time, each lane stepping from the wavefront's
 // current interval.  Query m-1 (x[n-1] itself) is patched at the end.
-template <bool MIXED, int VARIANT = kHoisted>
+template <bool MIXED, int VARIANT = kHoisted, bool WT = false>
 __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy, const double* so,
                                               const double* sinv, const int64_t* kq, int lo, int rs, int j0, int j1,
                                               double x0, double xl, double h, int64_t m, int64_t k0, int64_t k1,
@@ -1360,14 +1370,14 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
                     const double l1 = xa1 * v + bx1 * u;
                     const double c0 = cubic_term<MIXED>(xa0, bx0, ba2, up, vp);
                     const double c1 = cubic_term<MIXED>(xa1, bx1, ba2, up, vp);
-                    ob[0] = (l0 + (1.0 / 6.0) * c0) * inv;
-                    ob[kWave] = (l1 + (1.0 / 6.0) * c1) * inv;
+                    put_out<WT>(ob, (l0 + (1.0 / 6.0) * c0) * inv);
+                    put_out<WT>(ob + kWave, (l1 + (1.0 / 6.0) * c1) * inv);
                 } else if constexpr (VARIANT == kHorner) {
-                    ob[0] = horner(cf, q0 - av);
-                    ob[kWave] = horner(cf, q1 - av);
+                    put_out<WT>(ob, horner(cf, q0 - av));
+                    put_out<WT>(ob + kWave, horner(cf, q1 - av));
                 } else {
-                    ob[0] = interp_variant<VARIANT>(q0, av, bv, u, v, up, vp);
-                    ob[kWave] = interp_variant<VARIANT>(q1, av, bv, u, v, up, vp);
+                    put_out<WT>(ob, interp_variant<VARIANT>(q0, av, bv, u, v, up, vp));
+                    put_out<WT>(ob + kWave, interp_variant<VARIANT>(q1, av, bv, u, v, up, vp));
                 }
                 ob += 2 * kWave;
                 kr += (double)(2 * kWave);
@@ -1388,7 +1398,7 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
                 } else {
                     val = interp_variant<VARIANT>(q, av, bv, u, v, up, vp);
                 }
-                if (r + lane < ke) *ob = val;
+                if (r + lane < ke) put_out<WT>(ob, val);
                 ob += kWave;
                 kr += (double)kWave;
             }
@@ -1404,14 +1414,14 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
             while (tl + 1 <= t1 && kq[tl + 1 - j0] <= kk) ++tl;
             t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
             if (live)
-                out[k] = interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
-                                             so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]);
+                put_out<WT>(out + k, interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo],
+                                                         sy[tl + 1 - lo], so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]));
         }
     }
     if (k1 == m && m > 1 && lane == 0) {
         const int t = t1;  // query m-1 is x[n-1] itself, in the last interval
-        out[m - 1] = interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo], so[t - rs],
-                                         so[t + 1 - rs], sinv[t - j0]);
+        put_out<WT>(out + (m - 1), interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
+                                                       so[t - rs], so[t + 1 - rs], sinv[t - j0]));
     }
 }
 
