@@ -434,6 +434,10 @@ def bench_sweep(args):
 
         def noop():
             api.spline_noop_uniform(xs, m, out[:m])
+        st = torch.zeros((1,), dtype=torch.int32, device=dev)
+        api.spline_solve_uniform(xs, ys, 1e32, 1e32, m, out[:m], ypp[:n], st)
+        if int(st.cpu()[0]) != api.OK:
+            raise RuntimeError("sweep curve of %d knots rejected (status %d)" % (n, int(st.cpu()[0])))
         res = {}
         for name, fn in (("solve", solve), ("noop", noop)):
             fn()

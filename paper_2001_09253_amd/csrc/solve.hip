@@ -22,13 +22,17 @@
 // wavefronts per block (one solves, all evaluate) or one wavefront per block
 // (each solves and evaluates), a block's queries cut into shares when there
 // are many; sparse curves take one workgroup per block, and long curves with
-// very sparse queries one wavefront per block of 255 intervals.
+// very sparse queries one wavefront per block of 255 intervals.  Long curves
+// with up to a few queries per interval take one wavefront per segment of
+// many blocks ("chunks"), swept in order with the forward state carried from
+// chunk to chunk, so that only the segment's ends need a halo.
 // Every y'' is written by the one block that owns it and every query is
 // evaluated once (a block's first and last query are found by an exact search
 // over the query index), so results do not depend on the grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "spline_kernels.hpp"
@@ -276,6 +280,352 @@ __global__ __launch_bounds__(kWave) void solve_sparse_kernel(const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Long curves with at most a few queries per interval: one wavefront per
+// segment of consecutive chunks of 64 * CH rows (CH rows per lane), swept in
+// order.  The forward sweep's state (c', d') leaving a chunk enters the next
+// one exactly, so there is no halo inside a segment; a segment only starts
+// its sweep one chunk early (the chunk before it, swept forward and dropped:
+// the coupling it cuts is below (2/3)^(64 CH) max|y''|, the bound of the
+// halo above) and ends it one chunk late.  The back substitution of a chunk
+// needs y'' just after it, which the next chunk's backward scan gives: over
+// 64 CH rows its composed map has slope prod(-c') with |c'| <= 1/2, so it
+// fixes y'' at the next chunk's first row to within 2^-(64 CH) of the value
+// beyond it (exactly, at the curve's end, where c' = 0).  Per chunk and
+// wavefront the work is one forward scan and one backward scan, the paper's
+// recurrences per lane, then the chunk before is finished: y'' by back
+// substitution, its rows' y'' stored and the uniform queries of its
+// intervals evaluated.  Each lane walks its own CH intervals: it finds the
+// first query above its first knot once, then takes queries in order while
+// they do not pass the interval's right knot (the comparison that defines the
+// bracketing); an interval holding more than kStreamLaneQ queries is finished
+// by the whole wavefront.  Chunks inside the curve (no end row) take a path
+// without the end rows' cases.  The next chunk's knots and values are loaded
+// while the current one is solved.
+// ---------------------------------------------------------------------------
+constexpr int kStreamCH = 4;
+constexpr int kStreamWaves = 4;   // independent wavefronts per workgroup
+constexpr int kStreamLaneQ = 32;  // queries of one interval its own lane evaluates
+constexpr int64_t kStreamMinN = 1 << 17;  // shortest curve the streaming kernel takes
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// uniform_query for k held exactly as a double kd (md1 = m - 1, also exact):
+// the same bits (for k >= 1 only when !LOW).
+template <bool LOW = true>
+__device__ __forceinline__ double uniform_query_d(double x0, double xl, double h, double md1, double kd) {
+#pragma clang fp contract(off)
+    double step = kd * h;
+    double q = x0 + step;
+    q = (kd >= md1) ? xl : q;
+    if constexpr (LOW) q = (kd <= 0.0) ? x0 : q;
+    return q;
+}
+
+template <int CH>
+__global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int nc) {
+    constexpr int R = kWave * CH;  // rows per chunk
+    // knots and values of the last two chunks: sx[b][i] is knot i of the
+    // chunk (i = R: the next chunk's first), b the chunk's parity
+    __shared__ double lds_x[kStreamWaves][2][R + 1];
+    __shared__ double lds_y[kStreamWaves][2][R + 1];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int64_t seg = (int64_t)blockIdx.x * kStreamWaves + wid;
+    if (seg >= nseg) return;
+    const int n = (int)n64;
+    const bool nat_s = natural_end(sd);
+    const bool nat_e = natural_end(ed);
+    const int r0 = (int)(seg * nc * R);  // own rows [r0, r1)
+    const int r1 = (int)min<int64_t>((int64_t)r0 + (int64_t)nc * R, n64);
+    const int nct = (r1 - r0 + R - 1) / R;  // own chunks 0 .. nct-1
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    const double rh = (m > 1) ? 1.0 / h : 0.0;
+    const double md = (double)m;
+    const double md1 = (double)(m - 1);
+
+    // knots and values s-1 .. s+CH of a lane's rows s .. s+CH-1 (indices
+    // clamped into the curve; the clamped ones are never used)
+    double xc[CH + 2], yc[CH + 2], xn[CH + 2], yn[CH + 2];
+    auto load_chunk = [&](int t, double* xv, double* yv) {
+        const int s = r0 + t * R + lane * CH;
+#pragma unroll
+        for (int i = 0; i < CH + 2; ++i) {
+            const int j = min(max(s - 1 + i, 0), n - 1);
+            xv[i] = x[j];
+            yv[i] = y[j];
+        }
+    };
+    // a chunk without the curve's end rows and whose intervals end before
+    // the last knot (rows 1 .. n-3 only): its queries are above query 0 and
+    // below query m-1
+    auto interior = [&](int t) {
+        const int base = r0 + t * R;
+        return base >= 1 && base + R <= n - 2;
+    };
+    const int t_first = (r0 > 0) ? -1 : 0;
+    load_chunk(t_first, xc, yc);
+
+    // state of the sweep: (c', d') leaving the previous chunk
+    double cin = 0.0, din = 0.0;
+    // the previous chunk, swept forward, waiting for y'' beyond it (its
+    // knots and values wait in the LDS)
+    double wp[CH], dpv[CH];
+    Bwd sufp = bwd_identity();
+    int sp = 0, cntp = 0;
+    bool badp = false, fullp = false, bad_any = false;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) wp[i] = dpv[i] = 0.0;
+
+    // a1-a3 over one chunk: rows, forward map, scan, recurrence; leaves c'
+    // in w and d' in d and returns whether the chunk's knots are unordered
+    auto forward = [&](auto full_c, int s, int cnt, double* w, double* d) -> bool {
+        constexpr bool FULL = decltype(full_c)::value;
+        bool bad = false;
+        const double wprev0 = (FULL || (cnt > 0 && s >= 1)) ? xc[1] - xc[0] : 0.0;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            w[i] = 0.0;
+            if (FULL || i < cnt) {
+                const int j = s + i;
+                if ((FULL || j >= 1) && !(xc[1 + i] > xc[i])) bad = true;
+                w[i] = (FULL || j + 1 < n) ? xc[2 + i] - xc[1 + i] : 0.0;
+            }
+        }
+        {
+            double sprev = (FULL || (cnt > 0 && s >= 1)) ? (yc[1] - yc[0]) * fast_rcp(wprev0) : 0.0;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                d[i] = 0.0;
+                if (FULL || i < cnt) {
+                    const int j = s + i;
+                    const double snext = (FULL || j + 1 < n) ? (yc[2 + i] - yc[1 + i]) * fast_rcp(w[i]) : 0.0;
+                    if (!FULL && j == 0) d[i] = nat_s ? 0.0 : 6.0 * (snext - sd);
+                    else if (!FULL && j == n - 1) d[i] = nat_e ? 0.0 : 6.0 * (ed - sprev);
+                    else d[i] = 6.0 * (snext - sprev);
+                    sprev = snext;
+                }
+            }
+        }
+        // the chunk's forward map per lane (rows scaled by 2^-e, e the
+        // exponent of b), the exclusive scan over the wavefront, and the
+        // state entering each lane: the scanned map applied to (c', 1, d')
+        // leaving the previous chunk
+        Fwd acc = fwd_identity();
+        {
+            double wa = wprev0;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                if (FULL || i < cnt) {
+                    double a = wa, b = 2.0 * (wa + w[i]), c = w[i];
+                    if (!FULL) row_coeffs(s + i, n, nat_s, nat_e, wa, w[i], &a, &b, &c);
+                    int e;
+                    (void)frexp(b, &e);
+                    acc = fwd_apply_row_raw(acc, ldexp(a, -e), ldexp(b, -e), ldexp(c, -e), ldexp(d[i], -e));
+                    wa = w[i];
+                }
+            }
+        }
+        Fwd incl;
+        const Fwd pre = wave_excl_prefix_fwd_dpp<false>(acc, &incl);
+        const double P = pre.m00 * cin + pre.m01;
+        const double Q = pre.m10 * cin + pre.m11;
+        const double D = pre.r0 * cin + pre.r1 + pre.al * din;
+        const double iq = fast_rcp(Q);
+        double cp = P * iq;
+        double dp = D * iq;
+        {
+            double wa = wprev0;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                if (FULL || i < cnt) {
+                    const double wc = w[i];
+                    double a = wa, b = 2.0 * (wa + wc), c = wc;
+                    if (!FULL) row_coeffs(s + i, n, nat_s, nat_e, wa, wc, &a, &b, &c);
+                    const double inv = fast_rcp(b - a * cp);
+                    cp = c * inv;
+                    dp = (d[i] - a * dp) * inv;
+                    w[i] = cp;
+                    d[i] = dp;
+                    wa = wc;
+                }
+            }
+        }
+        // leaving the chunk: lane 63's last row (a chunk that is not full
+        // ends the curve, and nothing follows it)
+        cin = readlane_f64(cp, kWave - 1);
+        din = readlane_f64(dp, kWave - 1);
+        return __ballot(bad) != 0ull;
+    };
+
+    // a4 finished and a5/a6 for the previous chunk, given y'' at the first
+    // row after it
+    auto finish = [&](auto full_c, double yfirst, bool bad_next, int par) {
+        constexpr bool FULL = decltype(full_c)::value;
+        double o[CH + 1];
+        {
+            double yv = sufp.K * yfirst + sufp.H;
+#pragma unroll
+            for (int i = CH - 1; i >= 0; --i) {
+                o[i] = 0.0;
+                if (FULL || i < cntp) {
+                    yv = dpv[i] - wp[i] * yv;
+                    o[i] = yv;
+                }
+            }
+        }
+        if (ypp) {
+            const double nan = __builtin_nan("");
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (FULL || i < cntp) ypp[sp + i] = badp ? nan : o[i];
+        }
+        // y'' at the knot after the lane's rows: the next lane's first, or
+        // the next chunk's first for lane 63
+        const double onext = __shfl_down(o[0], 1);
+        o[CH] = (lane == kWave - 1) ? yfirst : onext;
+        if (badp || bad_next) return;  // unordered knots: no queries (status reports it)
+        wave_sync();
+        double xp[CH + 1], yp[CH + 1];
+#pragma unroll
+        for (int i = 0; i <= CH; ++i) {
+            xp[i] = lds_x[wid][par][lane * CH + i];
+            yp[i] = lds_y[wid][par][lane * CH + i];
+        }
+        // a5: the first query above the lane's first knot (query 0 for the
+        // curve's first knot)
+        const int64_t k0 = (sp == 0) ? 0 : (sp >= n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, xp[0]);
+        double kd = (double)k0;
+        double* out = yq + k0;
+        double q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const bool has = FULL || (i < cntp && sp + i <= n - 2);
+            Interval r;
+            r.a = xp[i];
+            r.b = xp[i + 1];
+            r.u = yp[i];
+            r.v = yp[i + 1];
+            r.up = o[i];
+            r.vp = o[i + 1];
+            const double ba = r.b - r.a;
+            r.inv = fast_rcp(ba);
+            r.ba2 = ba * ba;
+            // a6: the interval's queries are those not above its right knot
+            bool act;
+            for (int it = 0;; ++it) {
+                act = has && (FULL || kd < md) && !(q > r.b);
+                if (it == kStreamLaneQ || __ballot(act) == 0ull) break;
+                if (act) {
+                    *out++ = newint_rec(q, r);
+                    kd += 1.0;
+                    q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
+                }
+            }
+            // lanes with more: the rest of their interval by the whole
+            // wavefront, 64 consecutive queries per store
+            uint64_t big = __ballot(act);
+            if (big) {
+                const int64_t k = (int64_t)kd;
+                const int64_t kend = act ? first_query_above_r(x0, xl, h, rh, m, r.b) : k;
+                while (big) {
+                    const int L = __ffsll((long long)big) - 1;
+                    big &= big - 1;
+                    Interval rb;
+                    rb.a = readlane_f64(r.a, L);
+                    rb.b = readlane_f64(r.b, L);
+                    rb.u = readlane_f64(r.u, L);
+                    rb.v = readlane_f64(r.v, L);
+                    rb.up = readlane_f64(r.up, L);
+                    rb.vp = readlane_f64(r.vp, L);
+                    rb.inv = readlane_f64(r.inv, L);
+                    rb.ba2 = readlane_f64(r.ba2, L);
+                    const int64_t kb0 = readlane_i64(k, L);
+                    const int64_t ke = readlane_i64(kend, L);
+                    for (int64_t kk = kb0 + lane; kk < ke; kk += kWave)
+                        yq[kk] = newint_rec(uniform_query(x0, xl, h, m, kk), rb);
+                }
+                out = yq + kend;
+                kd = (double)kend;
+                q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
+            }
+        }
+    };
+
+    for (int t = t_first; t <= nct; ++t) {
+        if (t < nct) load_chunk(t + 1, xn, yn);
+        const int s = r0 + t * R + lane * CH;
+        const int cnt = max(0, min(n - s, CH));
+        const bool full = interior(t);
+        const int par = t & 1;
+        if (t >= 0) {
+            // this chunk's knots and values wait in the LDS for its queries
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                lds_x[wid][par][lane * CH + i] = xc[1 + i];
+                lds_y[wid][par][lane * CH + i] = yc[1 + i];
+            }
+            if (lane == kWave - 1) {
+                lds_x[wid][par][R] = xc[CH + 1];
+                lds_y[wid][par][R] = yc[CH + 1];
+            }
+        }
+        double w[CH], d[CH];
+        const bool bad = full ? forward(std::true_type{}, s, cnt, w, d) : forward(std::false_type{}, s, cnt, w, d);
+        bad_any = bad_any || bad;
+        if (t >= 0) {
+            // a4: the chunk's backward map per lane and the reversed scan;
+            // lane 0's inclusive map applied to 0 is y'' at the chunk's
+            // first row
+            Bwd bacc = bwd_identity();
+#pragma unroll
+            for (int i = CH - 1; i >= 0; --i)
+                if (full || i < cnt) bacc = bwd_compose(Bwd{-w[i], d[i]}, bacc);
+            Bwd bincl;
+            const Bwd suf = wave_excl_suffix_bwd(bacc, lane, &bincl);
+            const double yfirst = readlane_f64(bincl.H, 0);
+            if (t >= 1) {
+                if (fullp) finish(std::true_type{}, yfirst, bad, par ^ 1);
+                else finish(std::false_type{}, yfirst, bad, par ^ 1);
+            }
+            // this chunk now waits for y'' beyond it
+            sufp = suf;
+            sp = s;
+            cntp = cnt;
+            badp = bad;
+            fullp = full;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                wp[i] = w[i];
+                dpv[i] = d[i];
+            }
+        }
+        if (t < nct) {
+#pragma unroll
+            for (int i = 0; i < CH + 2; ++i) {
+                xc[i] = xn[i];
+                yc[i] = yn[i];
+            }
+        }
+    }
+    if (bad_any && status && lane == 0) atomicMin(status, kStatusOrder);
+}
+
+// ---------------------------------------------------------------------------
 // Dense curves, cooperative form: one workgroup of kCoopWaves wavefronts per
 // block of bk intervals (or per share of a block's queries).  The solve of a
 // block is one wavefront's work and its evaluation is cut among all of them:
@@ -505,6 +855,32 @@ static int launch_sparse_solve(const double* x, const double* y, int64_t n, doub
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
+// Segments of nc chunks: enough segments for every SIMD to hold a few
+// wavefronts, each long enough that its extra leading and trailing chunk
+// cost little (at most 64 chunks).
+template <int CH>
+static int stream_chunks_per_segment(int64_t n) {
+    const int64_t chunks = (n + kWave * CH - 1) / (kWave * CH);
+    const int64_t target = 4 * 4 * (int64_t)cu_count();
+    return (int)std::max<int64_t>(1, std::min<int64_t>(64, chunks / target));
+}
+
+template <int CH>
+static int launch_stream_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
+                               double* yq, double* ypp, int32_t* status, hipStream_t s, int nc = 0) {
+    if (nc <= 0) nc = stream_chunks_per_segment<CH>(n);
+    const int64_t rows = (int64_t)nc * kWave * CH;
+    const int64_t nseg = (n + rows - 1) / rows;
+    const int64_t groups = (nseg + kStreamWaves - 1) / kStreamWaves;
+    if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
+    // (default write-back stores: each store instruction here writes 64
+    // scattered results, which written-through stores send to memory as
+    // partial lines)
+    solve_stream_kernel<CH><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
+                                                                             nseg, nc);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
 // Dense curves: the cooperative kernel while the wavefront-per-block form
 // would leave the device short of wavefronts (every solve's latency then
 // sits on the critical path; sharing one solve among four wavefronts
@@ -525,10 +901,13 @@ static int launch_dense(const double* x, const double* y, int64_t n, double sd, 
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, hipStream_t s) {
     // (thresholds from timings on MI355X: the dense kernels already win at 16
-    // queries per interval, the blocks kernels at 4; the sparse kernel wins
-    // once queries are rarer than one per four intervals on long curves)
+    // queries per interval, the blocks kernels at 4; below 10 the streaming
+    // kernel wins on curves of 2^17 knots and more, by 3-4x at 2^22-2^26;
+    // the sparse kernel wins once queries are rarer than one per four
+    // intervals on shorter long curves)
     const double queries_per_knot = (double)m / (double)(n - 1);
     if (queries_per_knot >= 10.0) return launch_dense<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    if (n >= kStreamMinN) return launch_stream_solve<kStreamCH>(x, y, n, sd, ed, m, yq, ypp, status, s);
     if (queries_per_knot < 0.25 && n >= 65536)
         return launch_sparse_solve<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
     if (queries_per_knot * 64 >= 1024.0) return launch_blocks<64>(x, y, n, sd, ed, m, yq, ypp, status, s);

@@ -8,7 +8,10 @@ and the HIP path may be fed from it without sharing any of the method.
 Distributions follow the paper's benchmark generator (section "Curve
 Interpolation", step 5 of the methodology list): every new knot is the previous
 one plus an increment drawn from U(0,1), with a zero increment replaced by
-1e-4, and every value is a fresh U(0,1) draw.  The paper does not state the
+1e-4, and every value is a fresh U(0,1) draw.  An increment that does not move
+the knot in floating point (below half a unit in the last place of a large
+knot: at 2^28 knots, draws below about 1e-8) counts as zero, so that the
+knots stay strictly increasing.  The paper does not state the
 first knot; it is 0 here, as in its own test curves.  The increment and the
 value are two independent draws.  Random numbers come from NumPy's PCG64
 (``numpy.random.default_rng``).
@@ -54,6 +57,12 @@ def paper_curve(rng: np.random.Generator, n: int, x0: float = 0.0):
         # add.accumulate sums strictly left to right, so every knot is exactly
         # the previous knot plus its own increment
         np.add.accumulate(inc, out=x)
+        while True:
+            stuck = np.nonzero(x[1:] <= x[:-1])[0] + 1
+            if stuck.size == 0:
+                break
+            inc[stuck] = 1e-4
+            np.add.accumulate(inc, out=x)
     return x, val.astype(np.float64)
 
 

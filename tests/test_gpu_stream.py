@@ -1,0 +1,111 @@
+"""Long curves with at most a few queries per interval (spline_solve_uniform
+on curves of 2^17 knots and more below 10 queries per interval: one
+wavefront per segment of 256-row chunks, the forward state carried from
+chunk to chunk, a chunk's back substitution started from the next chunk's
+scan).  Every y'' and every query against the FP64 oracle at chunk and
+segment edges, on adversarial spacings and with intervals holding many
+queries; sampled at the sweep's largest size; unordered knots anywhere."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close, dev, host
+from paper_2001_09253_amd import api, workloads as w
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(1e32, 1e32), (0.0, 0.0), (-1.0, 1.0), (1e32, 0.5)]
+ROWS = 256  # rows per chunk
+
+
+def run(x, y, sd, ed, m):
+    xd, yd = dev(x), dev(y)
+    ypp = torch.full_like(xd, np.nan)
+    yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    api.spline_solve_uniform(xd, yd, sd, ed, m, yq, ypp, st)
+    return host(yq), host(ypp), int(host(st)[0])
+
+
+def check(x, y, sd, ed, m, what):
+    g_yq, g_ypp, st = run(x, y, sd, ed, m)
+    o_yq, o_ypp = oracle.spline_uniform(x, y, sd, ed, m)
+    assert st == api.OK, what
+    assert_close(g_ypp, o_ypp, "%s ypp" % what)
+    assert_close(g_yq, o_yq, "%s yq" % what)
+
+
+# (n, m): whole chunks, one row past a chunk, one row short, segments of
+# several chunks (n >= 2^21), densities from 1 query per 2^17 intervals to
+# 9.9 per interval, m = 1 and m = 2
+CASES = [(1 << 17, 1 << 17), (ROWS * 512 + 1, 50000), (ROWS * 512 - 1, 400000), (ROWS * 513, 1000000),
+         (ROWS * 513 + 2, 1297000), ((1 << 21) + 77, 1 << 21), ((1 << 22) + 255, 1 << 20), (1 << 18, 7),
+         (1 << 18, 1), (1 << 18, 2), (300001, 2)]
+
+
+@pytest.mark.parametrize("n,m", CASES)
+def test_stream_matches_oracle(n, m):
+    bc = (n + m) % len(BCS)
+    sd, ed = BCS[bc]
+    x, y = w.paper_curve(np.random.default_rng(n + 3 * m), n)
+    check(x, y, sd, ed, m, "n=%d m=%d bc=%d" % (n, m, bc))
+
+
+@pytest.mark.parametrize("kind", ["sawtooth_down", "sawtooth_up", "loguniform", "clustered"])
+def test_stream_adversarial_spacing(kind):
+    n = (1 << 18) + 129
+    x, y = w.spacing_curve(np.random.default_rng(17), n, kind)
+    check(x, y, 0.3, -0.7, n, kind)
+
+
+def test_stream_alternating_widths():
+    n = (1 << 18) + 3
+    x, y = w.alternating_curve(np.random.default_rng(5), n, small=1e-4, scale=1e3)
+    check(x, y, 1e32, 1e32, 2 * n, "alternating")
+
+
+@pytest.mark.parametrize("gap", [40.0, 3e3, 1e6])
+def test_stream_wide_intervals(gap):
+    # a few intervals far wider than the rest: they hold from tens of queries
+    # (the lane's own walk, then the whole wavefront past 32) to most of them
+    n = 1 << 18
+    rng = np.random.default_rng(int(gap))
+    widths = rng.random(n - 1) + 1e-3
+    for j in (5, 300, 777, 40000, 131071, n - 300, n - 2):
+        widths[j] *= gap
+    x = np.concatenate([[0.0], np.cumsum(widths)])
+    y = rng.standard_normal(n)
+    check(x, y, -1.0, 1.0, n, "gap %g" % gap)
+
+
+@pytest.mark.parametrize("n,m", [(1 << 26, 1 << 26), (1 << 28, 1 << 28)])
+def test_stream_full_size_sampled(n, m):
+    # the size sweep's large points (m = n): every y'' and a sample of the
+    # queries (the first, the last and random ones) against the oracle
+    x, y = w.paper_curve(np.random.default_rng(n % 1000 + 11), n)
+    ks = np.unique(np.concatenate([[0, 1, m - 2, m - 1], np.random.default_rng(10).integers(0, m, 4092)]))
+    xd, yd = dev(x), dev(y)
+    ypp = torch.empty_like(xd)
+    yq = torch.empty(m, dtype=torch.float64, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    api.spline_solve_uniform(xd, yd, 1e32, 1e32, m, yq, ypp, st)
+    o_vals, o_ypp = oracle.spline_uniform_sample(x, y, 1e32, 1e32, m, ks)
+    assert int(host(st)[0]) == api.OK
+    del xd, yd
+    g = yq[torch.as_tensor(ks, device="cuda")]
+    assert_close(host(g), o_vals, "stream full-size yq n=%d" % n)
+    del yq
+    assert_close(host(ypp), o_ypp, "stream full-size ypp n=%d" % n)
+
+
+@pytest.mark.parametrize("pos", [1, 255, 256, 257, 70000, (1 << 18) - 2, (1 << 18) - 1])
+def test_stream_bad_knots(pos):
+    n = 1 << 18
+    x, y = w.paper_curve(np.random.default_rng(pos), n)
+    x[pos] = x[pos - 1]
+    _, _, st = run(x, y, 0.0, 0.0, n)
+    assert st == api.E_ORDER
+    x[pos] = np.nan
+    _, _, st = run(x, y, 0.0, 0.0, 3)
+    assert st == api.E_ORDER
