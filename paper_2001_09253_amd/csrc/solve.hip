@@ -335,7 +335,7 @@ __device__ __forceinline__ double uniform_query_d(double x0, double xl, double h
 template <int CH>
 __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
-    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int nc) {
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int64_t chunks) {
     constexpr int R = kWave * CH;  // rows per chunk
     // knots and values of the last two chunks: sx[b][i] is knot i of the
     // chunk (i = R: the next chunk's first), b the chunk's parity
@@ -348,9 +348,12 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     const int n = (int)n64;
     const bool nat_s = natural_end(sd);
     const bool nat_e = natural_end(ed);
-    const int r0 = (int)(seg * nc * R);  // own rows [r0, r1)
-    const int r1 = (int)min<int64_t>((int64_t)r0 + (int64_t)nc * R, n64);
-    const int nct = (r1 - r0 + R - 1) / R;  // own chunks 0 .. nct-1
+    // own chunks [c0, c1) of the curve's chunks, split evenly over the
+    // segments: own rows from r0 up to c1 R (or the curve's end)
+    const int64_t c0 = seg * chunks / nseg;
+    const int64_t c1 = (seg + 1) * chunks / nseg;
+    const int r0 = (int)(c0 * R);
+    const int nct = (int)(c1 - c0);  // own chunks 0 .. nct-1
     const double x0 = x[0];
     const double xl = x[n - 1];
     const double h = uniform_step(x0, xl, m);
@@ -392,83 +395,121 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     for (int i = 0; i < CH; ++i) wp[i] = dpv[i] = 0.0;
 
     // a1-a3 over one chunk: rows, forward map, scan, recurrence; leaves c'
-    // in w and d' in d and returns whether the chunk's knots are unordered
-    auto forward = [&](auto full_c, int s, int cnt, double* w, double* d) -> bool {
+    // in w and d' in d and returns whether the chunk's knots are unordered.
+    // Without FULL the end rows take their own forms by selection (a rows
+    // past the curve's end is (0, 1, 0 | 0): c' = d' = 0, y'' = 0), so that
+    // both forms keep the same values live.
+    auto forward = [&](auto full_c, int s, double* w, double* d) -> bool {
         constexpr bool FULL = decltype(full_c)::value;
         bool bad = false;
-        const double wprev0 = (FULL || (cnt > 0 && s >= 1)) ? xc[1] - xc[0] : 0.0;
+        // widths: wl0 left of the first row, w[i] right of row i (zero where
+        // there is no interval)
+        const bool lo0 = FULL || (s >= 1 && s < n);
+        const double wl0 = lo0 ? xc[1] - xc[0] : 0.0;
+        if (lo0 && !(xc[1] > xc[0])) bad = true;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            w[i] = 0.0;
-            if (FULL || i < cnt) {
-                const int j = s + i;
-                if ((FULL || j >= 1) && !(xc[1 + i] > xc[i])) bad = true;
-                w[i] = (FULL || j + 1 < n) ? xc[2 + i] - xc[1 + i] : 0.0;
-            }
+            const int j = s + i;
+            const bool hi = FULL || j + 1 < n;
+            w[i] = hi ? xc[2 + i] - xc[1 + i] : 0.0;
+            if (i + 1 < CH && hi && !(xc[2 + i] > xc[1 + i])) bad = true;
         }
+        // right-hand sides from the slopes on either side
         {
-            double sprev = (FULL || (cnt > 0 && s >= 1)) ? (yc[1] - yc[0]) * fast_rcp(wprev0) : 0.0;
+            double sl = lo0 ? (yc[1] - yc[0]) * fast_rcp(wl0) : 0.0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                d[i] = 0.0;
-                if (FULL || i < cnt) {
-                    const int j = s + i;
-                    const double snext = (FULL || j + 1 < n) ? (yc[2 + i] - yc[1 + i]) * fast_rcp(w[i]) : 0.0;
-                    if (!FULL && j == 0) d[i] = nat_s ? 0.0 : 6.0 * (snext - sd);
-                    else if (!FULL && j == n - 1) d[i] = nat_e ? 0.0 : 6.0 * (ed - sprev);
-                    else d[i] = 6.0 * (snext - sprev);
-                    sprev = snext;
+                const int j = s + i;
+                const bool hi = FULL || j + 1 < n;
+                const double sr = hi ? (yc[2 + i] - yc[1 + i]) * fast_rcp(w[i]) : 0.0;
+                double di = 6.0 * (sr - sl);
+                if constexpr (!FULL) {
+                    di = (j == 0) ? (nat_s ? 0.0 : 6.0 * (sr - sd)) : di;
+                    di = (j == n - 1) ? (nat_e ? 0.0 : 6.0 * (ed - sl)) : di;
+                    di = (j >= n) ? 0.0 : di;
                 }
+                d[i] = di;
+                sl = sr;
             }
         }
+        // row i's (a, b, c): the paper's interior form from the widths; the
+        // natural ends and the rows past the end are (0, 1, 0)
+        auto coef = [&](int i, double wa, double wc, double& a, double& b, double& c) {
+            a = wa;
+            c = wc;
+            b = 2.0 * (wa + wc);
+            if constexpr (!FULL) {
+                const int j = s + i;
+                const bool unit = (j == 0 && nat_s) || (j == n - 1 && nat_e) || j >= n;
+                a = unit ? 0.0 : a;
+                c = unit ? 0.0 : c;
+                b = unit ? 1.0 : b;
+            }
+        };
         // the chunk's forward map per lane (rows scaled by 2^-e, e the
         // exponent of b), the exclusive scan over the wavefront, and the
         // state entering each lane: the scanned map applied to (c', 1, d')
         // leaving the previous chunk
         Fwd acc = fwd_identity();
         {
-            double wa = wprev0;
+            double wa = wl0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                if (FULL || i < cnt) {
-                    double a = wa, b = 2.0 * (wa + w[i]), c = w[i];
-                    if (!FULL) row_coeffs(s + i, n, nat_s, nat_e, wa, w[i], &a, &b, &c);
-                    int e;
-                    (void)frexp(b, &e);
-                    acc = fwd_apply_row_raw(acc, ldexp(a, -e), ldexp(b, -e), ldexp(c, -e), ldexp(d[i], -e));
-                    wa = w[i];
-                }
+                double a, b, c;
+                coef(i, wa, w[i], a, b, c);
+                int e;
+                (void)frexp(b, &e);
+                acc = fwd_apply_row_raw(acc, ldexp(a, -e), ldexp(b, -e), ldexp(c, -e), ldexp(d[i], -e));
+                wa = w[i];
             }
         }
-        Fwd incl;
-        const Fwd pre = wave_excl_prefix_fwd_dpp<false>(acc, &incl);
-        const double P = pre.m00 * cin + pre.m01;
-        const double Q = pre.m10 * cin + pre.m11;
-        const double D = pre.r0 * cin + pre.r1 + pre.al * din;
-        const double iq = fast_rcp(Q);
-        double cp = P * iq;
-        double dp = D * iq;
+        // inclusive scan: the state leaving each lane's rows is its inclusive
+        // map applied to (c', 1, d') leaving the previous chunk; a lane
+        // enters with the state the lane before it leaves with
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowShr1, 0xf>(acc));
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowShr2, 0xf>(acc));
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowShr4, 0xf>(acc));
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowShr8, 0xf>(acc));
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowBcast15, 0xa>(acc));
+        acc = fwd_comp<false>(acc, dpp_fwd<kDppRowBcast31, 0xc>(acc));
+        // (the rows' coefficients are formed again below rather than kept
+        // live across the scan)
+        double wl = wl0;
+        asm volatile("" : "+v"(wl));
+#pragma unroll
+        for (int i = 0; i < CH; ++i) asm volatile("" : "+v"(w[i]));
+        double cp, dp;
         {
-            double wa = wprev0;
+            const double P = acc.m00 * cin + acc.m01;
+            const double Q = acc.m10 * cin + acc.m11;
+            const double D = acc.r0 * cin + acc.r1 + acc.al * din;
+            const double iq = fast_rcp(Q);
+            const double cout = P * iq;
+            const double dout = D * iq;
+            // leaving the chunk: lane 63's state (a chunk that is not full
+            // ends the curve, and nothing follows it)
+            const double cnext = readlane_f64(cout, kWave - 1);
+            const double dnext = readlane_f64(dout, kWave - 1);
+            cp = dpp_f64<kDppWaveShr1, 0xf>(cin, cout);
+            dp = dpp_f64<kDppWaveShr1, 0xf>(din, dout);
+            cin = cnext;
+            din = dnext;
+        }
+        {
+            double wa = wl;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                if (FULL || i < cnt) {
-                    const double wc = w[i];
-                    double a = wa, b = 2.0 * (wa + wc), c = wc;
-                    if (!FULL) row_coeffs(s + i, n, nat_s, nat_e, wa, wc, &a, &b, &c);
-                    const double inv = fast_rcp(b - a * cp);
-                    cp = c * inv;
-                    dp = (d[i] - a * dp) * inv;
-                    w[i] = cp;
-                    d[i] = dp;
-                    wa = wc;
-                }
+                const double wc = w[i];
+                double a, b, c;
+                coef(i, wa, wc, a, b, c);
+                const double inv = fast_rcp(b - a * cp);
+                cp = c * inv;
+                dp = (d[i] - a * dp) * inv;
+                w[i] = cp;
+                d[i] = dp;
+                wa = wc;
             }
         }
-        // leaving the chunk: lane 63's last row (a chunk that is not full
-        // ends the curve, and nothing follows it)
-        cin = readlane_f64(cp, kWave - 1);
-        din = readlane_f64(dp, kWave - 1);
         return __ballot(bad) != 0ull;
     };
 
@@ -481,11 +522,8 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
             double yv = sufp.K * yfirst + sufp.H;
 #pragma unroll
             for (int i = CH - 1; i >= 0; --i) {
-                o[i] = 0.0;
-                if (FULL || i < cntp) {
-                    yv = dpv[i] - wp[i] * yv;
-                    o[i] = yv;
-                }
+                yv = dpv[i] - wp[i] * yv;
+                o[i] = yv;
             }
         }
         if (ypp) {
@@ -585,7 +623,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
             }
         }
         double w[CH], d[CH];
-        const bool bad = full ? forward(std::true_type{}, s, cnt, w, d) : forward(std::false_type{}, s, cnt, w, d);
+        const bool bad = full ? forward(std::true_type{}, s, w, d) : forward(std::false_type{}, s, w, d);
         bad_any = bad_any || bad;
         if (t >= 0) {
             // a4: the chunk's backward map per lane and the reversed scan;
@@ -593,8 +631,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
             // first row
             Bwd bacc = bwd_identity();
 #pragma unroll
-            for (int i = CH - 1; i >= 0; --i)
-                if (full || i < cnt) bacc = bwd_compose(Bwd{-w[i], d[i]}, bacc);
+            for (int i = CH - 1; i >= 0; --i) bacc = bwd_compose(Bwd{-w[i], d[i]}, bacc);
             Bwd bincl;
             const Bwd suf = wave_excl_suffix_bwd(bacc, lane, &bincl);
             const double yfirst = readlane_f64(bincl.H, 0);
@@ -855,29 +892,27 @@ static int launch_sparse_solve(const double* x, const double* y, int64_t n, doub
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
-// Segments of nc chunks: enough segments for every SIMD to hold a few
-// wavefronts, each long enough that its extra leading and trailing chunk
-// cost little (at most 64 chunks).
-template <int CH>
-static int stream_chunks_per_segment(int64_t n) {
-    const int64_t chunks = (n + kWave * CH - 1) / (kWave * CH);
-    const int64_t target = 4 * 4 * (int64_t)cu_count();
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, chunks / target));
-}
+// Segments of about kStreamSegChunks chunks (the extra leading and trailing
+// chunk then cost 3%), but at least two per SIMD (2048 on MI355X) while
+// each keeps kStreamMinChunks chunks or more: measured at m = n, 2^24-2^28
+// knots, within 5% of the best count at every size.
+constexpr int64_t kStreamSegChunks = 64;
+constexpr int64_t kStreamMinChunks = 4;
 
 template <int CH>
 static int launch_stream_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
-                               double* yq, double* ypp, int32_t* status, hipStream_t s, int nc = 0) {
-    if (nc <= 0) nc = stream_chunks_per_segment<CH>(n);
-    const int64_t rows = (int64_t)nc * kWave * CH;
-    const int64_t nseg = (n + rows - 1) / rows;
+                               double* yq, double* ypp, int32_t* status, hipStream_t s, int64_t nseg = 0) {
+    const int64_t chunks = (n + kWave * CH - 1) / (kWave * CH);
+    if (nseg <= 0)
+        nseg = std::max(chunks / kStreamSegChunks, std::min<int64_t>(8 * cu_count(), chunks / kStreamMinChunks));
+    nseg = std::max<int64_t>(1, std::min(nseg, chunks));
     const int64_t groups = (nseg + kStreamWaves - 1) / kStreamWaves;
     if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
     // (default write-back stores: each store instruction here writes 64
     // scattered results, which written-through stores send to memory as
     // partial lines)
     solve_stream_kernel<CH><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
-                                                                             nseg, nc);
+                                                                             nseg, chunks);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
