@@ -13,6 +13,8 @@ Workloads (--workload):
            (the paper's 13-knot / 2048-point worked size scaled 1000x), seed 0
   small    1 curve, n = 13, m = 2048 (the worked size itself)
   plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
+  long     1 curve, n = m = 2^28 (the size sweep's largest point: one query
+           per interval, the streaming kernel)
   batched  4096 curves, sizes log-uniform 0.1x..10x of the worked size, one
            launch per step over autotuned work items (timed as a hipGraph
            replay and as a direct launch; the faster gives the value)
@@ -65,7 +67,7 @@ def cpu_cores_used(n):
     return int(n)
 
 
-def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
+def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32, cpu_sample=None):
     import numpy as np
     import torch
 
@@ -79,21 +81,24 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     yq = torch.empty(m, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     sd, ed = inst.start_deriv, inst.end_deriv
-    # the two-launch form (build, then evaluate), timed per kernel for reference
-    for _ in range(args.warmup):
-        api.spline_build(x, y, sd, ed, ypp)
-        api.spline_eval_uniform(x, y, ypp, m, yq)
+    # the two-launch form (build, then evaluate), timed per kernel for
+    # reference (its build takes curves of up to SOLVE_MAX_N_BLOCK knots)
     K = args.steps
-    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    for k in range(K):
-        ev2[k][0].record(stream)
-        api.spline_build(x, y, sd, ed, ypp)
-        ev2[k][1].record(stream)
-        api.spline_eval_uniform(x, y, ypp, m, yq)
-        ev2[k][2].record(stream)
-    torch.cuda.synchronize()
-    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / K
-    eval_ms = sum(e[1].elapsed_time(e[2]) for e in ev2) / K
+    build_ms = eval_ms = None
+    if n <= api.MAX_N_BLOCK:
+        for _ in range(args.warmup):
+            api.spline_build(x, y, sd, ed, ypp)
+            api.spline_eval_uniform(x, y, ypp, m, yq)
+        ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        for k in range(K):
+            ev2[k][0].record(stream)
+            api.spline_build(x, y, sd, ed, ypp)
+            ev2[k][1].record(stream)
+            api.spline_eval_uniform(x, y, ypp, m, yq)
+            ev2[k][2].record(stream)
+        torch.cuda.synchronize()
+        build_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / K
+        eval_ms = sum(e[1].elapsed_time(e[2]) for e in ev2) / K
     # the timed path: one launch per step (build and evaluate fused); with
     # --variant, the one-launch kernel with one of the paper's evaluation
     # formulas
@@ -165,7 +170,14 @@ def bench_single(args, n, m, workload_name, sd=1e32, ed=1e32):
     }
     out["path_frac_peak"] = out["path_gbs"] / HBM_PEAK_GBS
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_single(inst, args.cpu_seconds)
+        if cpu_sample is None:
+            out["cpu_baseline"] = cpu_baseline_single(inst, args.cpu_seconds)
+        else:
+            # a bounded sample: the curve's first cpu_sample knots, queries
+            # at the same density
+            k = int(cpu_sample)
+            sub = workloads.Instance(inst.x[:k], inst.y[:k], sd, ed, max(2, int(round(m * (k - 1) / (n - 1)))))
+            out["cpu_baseline"] = cpu_baseline_single(sub, args.cpu_seconds)
     return out
 
 
@@ -523,7 +535,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "plain2x", "batched", "mixed", "served", "copy", "sweep"])
+                    choices=["plain", "small", "plain2x", "long", "batched", "mixed", "served", "copy", "sweep"])
     ap.add_argument("--variant", default=None,
                     choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul", "horner"],
                     help="single-curve workloads: time this evaluation formula on the one-launch kernel")
@@ -545,6 +557,9 @@ def main():
         out = bench_single(args, 13, 2048, "small: 1 curve, n=13, m=2048 uniform queries")
     elif args.workload == "plain2x":
         out = bench_single(args, 13000, 1 << 27, "plain2x: 1 curve, n=13000, m=2^27 uniform queries")
+    elif args.workload == "long":
+        out = bench_single(args, 1 << 28, 1 << 28, "long: 1 curve, n=m=2^28 (the size sweep's largest point)",
+                           cpu_sample=1 << 22)
     elif args.workload in ("batched", "mixed"):
         from paper_2001_09253_amd import api
         out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)

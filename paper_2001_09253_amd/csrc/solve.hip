@@ -892,19 +892,49 @@ static int launch_sparse_solve(const double* x, const double* y, int64_t n, doub
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
-// Segments of about kStreamSegChunks chunks (the extra leading and trailing
-// chunk then cost 3%), but at least two per SIMD (2048 on MI355X) while
-// each keeps kStreamMinChunks chunks or more: measured at m = n, 2^24-2^28
-// knots, within 5% of the best count at every size.
+// Wavefronts of the streaming kernel the device holds at once (its register
+// use allows 3 per SIMD).
+template <int CH>
+static int64_t stream_resident_waves() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_stream_kernel<CH>, kWave * kStreamWaves, 0) !=
+                hipSuccess || v <= 0)
+            v = 1;
+        cached[dev] = v;
+    }
+    return (int64_t)cached[dev] * kStreamWaves * cu_count();
+}
+
+// Segments: every SIMD must get the same number of them, since a SIMD holding
+// one segment more than the others finishes last (measured: 2144 segments
+// ran 1.4x slower than 2048).  Long curves (kStreamMinChunks chunks per
+// resident wavefront or more) take whole rounds of the resident wavefronts,
+// with segments of at most kStreamSegChunks chunks; shorter ones one round
+// of a multiple of the SIMD count, with at least 2 chunks per segment (a
+// segment also sweeps one chunk before and one after its own).
 constexpr int64_t kStreamSegChunks = 64;
-constexpr int64_t kStreamMinChunks = 4;
+constexpr int64_t kStreamMinChunks = 8;
+
+template <int CH>
+static int64_t stream_segments(int64_t chunks) {
+    const int64_t slots = stream_resident_waves<CH>();
+    const int64_t simds = 4 * (int64_t)cu_count();
+    if (chunks >= slots * kStreamMinChunks)
+        return slots * ((chunks + slots * kStreamSegChunks - 1) / (slots * kStreamSegChunks));
+    const int64_t want = std::min(slots, chunks / 2);
+    const int64_t even = (want / simds) * simds;
+    return even > 0 ? even : std::max<int64_t>(1, want);
+}
 
 template <int CH>
 static int launch_stream_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
                                double* yq, double* ypp, int32_t* status, hipStream_t s, int64_t nseg = 0) {
     const int64_t chunks = (n + kWave * CH - 1) / (kWave * CH);
-    if (nseg <= 0)
-        nseg = std::max(chunks / kStreamSegChunks, std::min<int64_t>(8 * cu_count(), chunks / kStreamMinChunks));
+    if (nseg <= 0) nseg = stream_segments<CH>(chunks);
     nseg = std::max<int64_t>(1, std::min(nseg, chunks));
     const int64_t groups = (nseg + kStreamWaves - 1) / kStreamWaves;
     if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
