@@ -183,7 +183,13 @@ int spline_eval_uniform(const double *x, const double *y, const double *ypp, int
  * the dropped coupling, bounded through the paper's recurrences, is below
  * 2^-60 max|y''|, else 128 rows (below 1e-21 max|y''| by the diagonal
  * dominance the paper proves); curves shorter than a block plus both halos
- * are solved whole.  The kernel is chosen by the query density m/(n-1).
+ * are solved whole.  On curves of 2^17 knots or more with fewer than 10
+ * queries per interval each wavefront instead sweeps a run of 256-row blocks
+ * in order, carrying the forward elimination's state (c', d') exactly from
+ * block to block, so that only the run's ends take a halo (one block before
+ * it, below (2/3)^256 max|y''|; the back substitution of a block starts from
+ * the next block's backward scan, within 2^-256 max|y''|).  The kernel is
+ * chosen by the query density m/(n-1) and by n.
  * x, y: n device doubles; yq: m device doubles (output); ypp: nullable, n
  * device doubles (output).  status: nullable device int32 that the call
  * leaves unchanged unless it finds unordered knots, in which case it is set
