@@ -21,10 +21,9 @@
 // Dense curves (many queries per interval) take either a workgroup of four
 // wavefronts per block (one solves, all evaluate) or one wavefront per block
 // (each solves and evaluates), a block's queries cut into shares when there
-// are many; sparse curves take one workgroup per block, and long curves with
-// very sparse queries one wavefront per block of 255 intervals.  Long curves
-// with up to a few queries per interval take one wavefront per segment of
-// many blocks ("chunks"), swept in order with the forward state carried from
+// are many; sparse curves take one workgroup per block.  Long curves with up
+// to a few queries per interval take one wavefront per segment of many
+// blocks ("chunks"), swept in order with the forward state carried from
 // chunk to chunk, so that only the segment's ends need a halo.
 // Every y'' is written by the one block that owns it and every query is
 // evaluated once (a block's first and last query are found by an exact search
@@ -214,72 +213,6 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Long curves with sparse queries: one wavefront per block of up to kSparseBK
-// intervals, the adaptive halo as above, the span solved with up to
-// kSparseCH rows per lane (the uniform fallback halo's 255 + 1 + 2 * 128
-// rows fit), the queries evaluated 64 at a time.  More rows per lane make
-// the per-row work of the solve (each lane's serial part) dominate its fixed
-// cost (the wavefront scans), which is what a sparse block needs.
-// ---------------------------------------------------------------------------
-constexpr int kSparseBK = 255;
-constexpr int kSparseCH = 8;  // 512 rows >= kSparseBK + 1 + 2 * kHalo
-
-struct SparseSmem {
-    double sx[kWave * kSparseCH + 2];
-    double sy[kWave * kSparseCH + 2];
-    double so[kWave * kSparseCH + 2];
-    double inv[kSparseBK];
-    int32_t bq[kSparseBK + 1];
-};
-
-template <int VARIANT, bool WT>
-__global__ __launch_bounds__(kWave) void solve_sparse_kernel(const double* __restrict__ x,
-                                                             const double* __restrict__ y, int64_t n64, double sd,
-                                                             double ed, int64_t m, double* __restrict__ yq,
-                                                             double* __restrict__ ypp, int32_t* __restrict__ status,
-                                                             int bk) {
-    __shared__ SparseSmem sm;
-    const int lane = threadIdx.x;
-    const int n = (int)n64;
-    const int j0 = (int)((int64_t)blockIdx.x * bk);
-    const int j1 = min(j0 + bk, n - 1);  // intervals [j0, j1)
-    int rs, re;
-    adaptive_halo(x, n, j0, j1, kHaloEps, kHalo, lane, &rs, &re);
-    // a1-a4 over rows [rs, re), compiled for the fewest rows per lane that
-    // hold the span
-    bool bad;
-    if (re - rs <= 2 * kWave)
-        bad = build_span<kWave, 2, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx, nullptr,
-                                                            nullptr, SoloGroup{}, lane, sm.sy, sm.so);
-    else if (re - rs <= 5 * kWave)
-        bad = build_span<kWave, 5, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx, nullptr,
-                                                            nullptr, SoloGroup{}, lane, sm.sy, sm.so);
-    else
-        bad = build_span<kWave, kSparseCH, true, SoloGroup, false>(x, y, n, rs, re, sd, ed, nullptr, nullptr, sm.sx,
-                                                                    nullptr, nullptr, SoloGroup{}, lane, sm.sy,
-                                                                    sm.so);
-    if (bad && status && lane == 0) atomicMin(status, kStatusOrder);
-    const int lo = max(rs - 1, 0);  // knot j staged at [j - lo]; y'' of row i at so[i - rs]
-    if (ypp) {
-        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
-        for (int j = j0 + lane; j < jend; j += kWave) ypp[j] = sm.so[j - rs];
-    }
-    for (int t = j0 + lane; t < j1; t += kWave) sm.inv[t - j0] = 1.0 / (sm.sx[t + 1 - lo] - sm.sx[t - lo]);
-    // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the
-    // first block)
-    const double x0 = x[0];
-    const double xl = x[n - 1];
-    const double h = uniform_step(x0, xl, m);
-    const double rh = (m > 1) ? 1.0 / h : 0.0;
-    const int64_t ka = (j0 == 0) ? 0 : first_query_above_r(x0, xl, h, rh, m, sm.sx[j0 - lo]);
-    const int64_t kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, sm.sx[j1 - lo]);
-    wave_sync();
-    if (ka >= kb) return;
-    wave_eval_block<false, false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh,
-                                               m, ka, kb, yq, lane);
-}
-
-// ---------------------------------------------------------------------------
 // Long curves with at most a few queries per interval: one wavefront per
 // segment of consecutive chunks of 64 * CH rows (CH rows per lane), swept in
 // order.  The forward sweep's state (c', d') leaving a chunk enters the next
@@ -305,7 +238,7 @@ __global__ __launch_bounds__(kWave) void solve_sparse_kernel(const double* __res
 constexpr int kStreamCH = 4;
 constexpr int kStreamWaves = 4;   // independent wavefronts per workgroup
 constexpr int kStreamLaneQ = 32;  // queries of one interval its own lane evaluates
-constexpr int64_t kStreamMinN = 1 << 17;  // shortest curve the streaming kernel takes
+constexpr int64_t kStreamMinN = 163840;  // shortest curve the streaming kernel takes
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const long long b = __double_as_longlong(v);
@@ -879,19 +812,6 @@ static int launch_coop_solve(const double* x, const double* y, int64_t n, double
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
-template <int VARIANT>
-static int launch_sparse_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
-                               double* yq, double* ypp, int32_t* status, hipStream_t s, int bk = kSparseBK) {
-    bk = std::max(1, std::min(bk, kSparseBK));
-    const int64_t nblocks = (n - 1 + bk - 1) / bk;
-    if (nblocks > 0x7fffffffLL) return SOLVE_E_SIZE;
-    if (write_through(m))
-        solve_sparse_kernel<VARIANT, true><<<(unsigned)nblocks, kWave, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk);
-    else
-        solve_sparse_kernel<VARIANT, false><<<(unsigned)nblocks, kWave, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk);
-    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
-}
-
 // Wavefronts of the streaming kernel the device holds at once (its register
 // use allows 3 per SIMD).
 template <int CH>
@@ -966,16 +886,13 @@ static int launch_dense(const double* x, const double* y, int64_t n, double sd, 
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, hipStream_t s) {
     // (thresholds from timings on MI355X: the dense kernels already win at 16
-    // queries per interval, the blocks kernels at 4; below 10 the streaming
-    // kernel wins on curves of 2^17 knots and more, by 3-4x at 2^22-2^26;
-    // the sparse kernel wins once queries are rarer than one per four
-    // intervals on shorter long curves)
+    // queries per interval, the blocks kernel at 4; below 10 the streaming
+    // kernel wins from about 160K knots at up to 4 queries per interval (by
+    // 3-4x at 2^22-2^26 knots) and from 2^20 knots at up to 10)
     const double queries_per_knot = (double)m / (double)(n - 1);
     if (queries_per_knot >= 10.0) return launch_dense<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
-    if (n >= kStreamMinN) return launch_stream_solve<kStreamCH>(x, y, n, sd, ed, m, yq, ypp, status, s);
-    if (queries_per_knot < 0.25 && n >= 65536)
-        return launch_sparse_solve<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
-    if (queries_per_knot * 64 >= 1024.0) return launch_blocks<64>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    if (n >= kStreamMinN && (queries_per_knot < 4.0 || n >= ((int64_t)1 << 20)))
+        return launch_stream_solve<kStreamCH>(x, y, n, sd, ed, m, yq, ypp, status, s);
     return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, s);
 }
 

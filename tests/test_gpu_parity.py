@@ -266,9 +266,9 @@ def test_solve_uniform_adaptive_halo_adversarial_spacing(kind, bc):
 
 @pytest.mark.parametrize("kind", ["alternating", "sawtooth_down", "loguniform", "clustered"])
 def test_solve_uniform_sparse_long_curves(kind):
-    # long curves with far fewer queries than intervals take the kernel that
-    # solves blocks of 255 intervals; the alternating widths force its uniform
-    # fallback halo (the widest span it holds)
+    # long curves with far fewer queries than intervals take the block kernel
+    # (256 intervals per block, per-query search); the alternating widths
+    # force its uniform fallback halo (the widest span it holds)
     n, m = 70000, 3000
     rng = np.random.default_rng(41)
     if kind == "alternating":

@@ -1,8 +1,8 @@
 """Long curves with at most a few queries per interval (spline_solve_uniform
-on curves of 2^17 knots and more below 10 queries per interval: one
-wavefront per segment of 256-row chunks, the forward state carried from
-chunk to chunk, a chunk's back substitution started from the next chunk's
-scan).  Every y'' and every query against the FP64 oracle at chunk and
+on curves of 163,840 knots and more below 4 queries per interval, and of 2^20
+and more below 10: one wavefront per segment of 256-row chunks, the forward
+state carried from chunk to chunk, a chunk's back substitution started from
+the next chunk's scan).  Every y'' and every query against the FP64 oracle at chunk and
 segment edges, on adversarial spacings and with intervals holding many
 queries; sampled at the sweep's largest size; unordered knots anywhere."""
 import numpy as np
@@ -37,11 +37,11 @@ def check(x, y, sd, ed, m, what):
 
 
 # (n, m): whole chunks, one row past a chunk, one row short, segments of
-# several chunks (n >= 2^21), densities from 1 query per 2^17 intervals to
+# several chunks (n >= 2^21), densities from 1 query per 2^18 intervals to
 # 9.9 per interval, m = 1 and m = 2
-CASES = [(1 << 17, 1 << 17), (ROWS * 512 + 1, 50000), (ROWS * 512 - 1, 400000), (ROWS * 513, 1000000),
-         (ROWS * 513 + 2, 1297000), ((1 << 21) + 77, 1 << 21), ((1 << 22) + 255, 1 << 20), (1 << 18, 7),
-         (1 << 18, 1), (1 << 18, 2), (300001, 2)]
+CASES = [(ROWS * 640, ROWS * 640), (ROWS * 640 + 1, 50000), (ROWS * 700 - 1, 400000), (ROWS * 701, 700000),
+         ((1 << 20) + 2, 10380000), ((1 << 20) + 3 * ROWS, 5 << 20), ((1 << 21) + 77, 1 << 21),
+         ((1 << 22) + 255, 1 << 20), (1 << 18, 7), (1 << 18, 1), (1 << 18, 2), (300001, 2)]
 
 
 @pytest.mark.parametrize("n,m", CASES)
