@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     __shared__ double lds_x[kStreamWaves][2][R + 1];
     __shared__ double lds_y[kStreamWaves][2][R + 1];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // (held in a scalar register)
     const int64_t seg = (int64_t)blockIdx.x * kStreamWaves + wid;
     if (seg >= nseg) return;
     const int n = (int)n64;
@@ -294,17 +294,27 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     const double md = (double)m;
     const double md1 = (double)(m - 1);
 
-    // knots and values s-1 .. s+CH of a lane's rows s .. s+CH-1 (indices
-    // clamped into the curve; the clamped ones are never used)
-    double xc[CH + 2], yc[CH + 2], xn[CH + 2], yn[CH + 2];
-    auto load_chunk = [&](int t, double* xv, double* yv) {
-        const int s = r0 + t * R + lane * CH;
+    // knots and values s .. s+CH-1 of a lane's rows s .. s+CH-1, and the
+    // chunk's neighbours, knots base-1 and base+R (uniform, scalar loads);
+    // indices clamped into the curve (the clamped ones are never used).  A
+    // lane takes knots s-1 and s+CH from the lanes beside it (DPP).
+    double xc[CH], yc[CH], xn[CH], yn[CH];
+    double xlc, ylc, xhc, yhc, xln, yln, xhn, yhn;
+    auto load_chunk = [&](int t, double* xv, double* yv, double& xlo, double& ylo, double& xhi, double& yhi) {
+        const int base = r0 + t * R;
+        const int s = base + lane * CH;
 #pragma unroll
-        for (int i = 0; i < CH + 2; ++i) {
-            const int j = min(max(s - 1 + i, 0), n - 1);
+        for (int i = 0; i < CH; ++i) {
+            const int j = min(s + i, n - 1);
             xv[i] = x[j];
             yv[i] = y[j];
         }
+        const int jl = min(max(base - 1, 0), n - 1);  // (base passes n for the chunk after the curve's end)
+        const int jh = min(base + R, n - 1);
+        xlo = x[jl];
+        ylo = y[jl];
+        xhi = x[jh];
+        yhi = y[jh];
     };
     // a chunk without the curve's end rows and whose intervals end before
     // the last knot (rows 1 .. n-3 only): its queries are above query 0 and
@@ -314,7 +324,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
         return base >= 1 && base + R <= n - 2;
     };
     const int t_first = (r0 > 0) ? -1 : 0;
-    load_chunk(t_first, xc, yc);
+    load_chunk(t_first, xc, yc, xlc, ylc, xhc, yhc);
 
     // state of the sweep: (c', d') leaving the previous chunk
     double cin = 0.0, din = 0.0;
@@ -335,26 +345,37 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     auto forward = [&](auto full_c, int s, double* w, double* d) -> bool {
         constexpr bool FULL = decltype(full_c)::value;
         bool bad = false;
+        // knots and values s-1 .. s+CH
+        double xf[CH + 2], yf[CH + 2];
+        xf[0] = dpp_f64<kDppWaveShr1, 0xf>(xlc, xc[CH - 1]);
+        yf[0] = dpp_f64<kDppWaveShr1, 0xf>(ylc, yc[CH - 1]);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            xf[1 + i] = xc[i];
+            yf[1 + i] = yc[i];
+        }
+        xf[CH + 1] = dpp_f64<kDppWaveShl1, 0xf>(xhc, xc[0]);
+        yf[CH + 1] = dpp_f64<kDppWaveShl1, 0xf>(yhc, yc[0]);
         // widths: wl0 left of the first row, w[i] right of row i (zero where
         // there is no interval)
         const bool lo0 = FULL || (s >= 1 && s < n);
-        const double wl0 = lo0 ? xc[1] - xc[0] : 0.0;
-        if (lo0 && !(xc[1] > xc[0])) bad = true;
+        const double wl0 = lo0 ? xf[1] - xf[0] : 0.0;
+        if (lo0 && !(xf[1] > xf[0])) bad = true;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const int j = s + i;
             const bool hi = FULL || j + 1 < n;
-            w[i] = hi ? xc[2 + i] - xc[1 + i] : 0.0;
-            if (i + 1 < CH && hi && !(xc[2 + i] > xc[1 + i])) bad = true;
+            w[i] = hi ? xf[2 + i] - xf[1 + i] : 0.0;
+            if (i + 1 < CH && hi && !(xf[2 + i] > xf[1 + i])) bad = true;
         }
         // right-hand sides from the slopes on either side
         {
-            double sl = lo0 ? (yc[1] - yc[0]) * fast_rcp(wl0) : 0.0;
+            double sl = lo0 ? (yf[1] - yf[0]) * fast_rcp(wl0) : 0.0;
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const int j = s + i;
                 const bool hi = FULL || j + 1 < n;
-                const double sr = hi ? (yc[2 + i] - yc[1 + i]) * fast_rcp(w[i]) : 0.0;
+                const double sr = hi ? (yf[2 + i] - yf[1 + i]) * fast_rcp(w[i]) : 0.0;
                 double di = 6.0 * (sr - sl);
                 if constexpr (!FULL) {
                     di = (j == 0) ? (nat_s ? 0.0 : 6.0 * (sr - sd)) : di;
@@ -538,7 +559,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     };
 
     for (int t = t_first; t <= nct; ++t) {
-        if (t < nct) load_chunk(t + 1, xn, yn);
+        if (t < nct) load_chunk(t + 1, xn, yn, xln, yln, xhn, yhn);
         const int s = r0 + t * R + lane * CH;
         const int cnt = max(0, min(n - s, CH));
         const bool full = interior(t);
@@ -547,12 +568,12 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
             // this chunk's knots and values wait in the LDS for its queries
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                lds_x[wid][par][lane * CH + i] = xc[1 + i];
-                lds_y[wid][par][lane * CH + i] = yc[1 + i];
+                lds_x[wid][par][lane * CH + i] = xc[i];
+                lds_y[wid][par][lane * CH + i] = yc[i];
             }
             if (lane == kWave - 1) {
-                lds_x[wid][par][R] = xc[CH + 1];
-                lds_y[wid][par][R] = yc[CH + 1];
+                lds_x[wid][par][R] = xhc;
+                lds_y[wid][par][R] = yhc;
             }
         }
         double w[CH], d[CH];
@@ -586,10 +607,14 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
         }
         if (t < nct) {
 #pragma unroll
-            for (int i = 0; i < CH + 2; ++i) {
+            for (int i = 0; i < CH; ++i) {
                 xc[i] = xn[i];
                 yc[i] = yn[i];
             }
+            xlc = xln;
+            ylc = yln;
+            xhc = xhn;
+            yhc = yhn;
         }
     }
     if (bad_any && status && lane == 0) atomicMin(status, kStatusOrder);
@@ -813,7 +838,7 @@ static int launch_coop_solve(const double* x, const double* y, int64_t n, double
 }
 
 // Wavefronts of the streaming kernel the device holds at once (its register
-// use allows 3 per SIMD).
+// use allows 4 per SIMD).
 template <int CH>
 static int64_t stream_resident_waves() {
     static int cached[64] = {0};

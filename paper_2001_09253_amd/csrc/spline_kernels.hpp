@@ -298,7 +298,7 @@ __device__ __forceinline__ Fwd dpp_fwd(const Fwd& v) {
 // DPP controls (GFX9): shift right within rows of 16 lanes, broadcast lane 15
 // of a row to the next row, lane 31 to rows 2 and 3, shift the wave by one.
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
 
 // Inclusive and exclusive prefix (in lane order, later lanes outer) of Fwd
 // maps over one wavefront with DPP moves (no LDS round trips): a Hillis-Steele
