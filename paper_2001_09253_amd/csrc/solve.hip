@@ -265,7 +265,7 @@ __device__ __forceinline__ double uniform_query_d(double x0, double xl, double h
     return q;
 }
 
-template <int CH>
+template <int CH, bool VEC>
 __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
     double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int64_t chunks) {
@@ -303,11 +303,25 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     auto load_chunk = [&](int t, double* xv, double* yv, double& xlo, double& ylo, double& xhi, double& yhi) {
         const int base = r0 + t * R;
         const int s = base + lane * CH;
+        if (VEC && CH % 2 == 0 && base + R <= n) {
+            // 16 bytes per load (x and y 16-byte aligned, s even, the chunk
+            // inside the curve)
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int j = min(s + i, n - 1);
-            xv[i] = x[j];
-            yv[i] = y[j];
+            for (int i = 0; i < CH; i += 2) {
+                const double2 xx = *reinterpret_cast<const double2*>(x + s + i);
+                const double2 yy = *reinterpret_cast<const double2*>(y + s + i);
+                xv[i] = xx.x;
+                xv[i + 1] = xx.y;
+                yv[i] = yy.x;
+                yv[i + 1] = yy.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int j = min(s + i, n - 1);
+                xv[i] = x[j];
+                yv[i] = y[j];
+            }
         }
         const int jl = min(max(base - 1, 0), n - 1);  // (base passes n for the chunk after the curve's end)
         const int jh = min(base + R, n - 1);
@@ -846,7 +860,7 @@ static int64_t stream_resident_waves() {
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     if (!cached[dev]) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_stream_kernel<CH>, kWave * kStreamWaves, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_stream_kernel<CH, true>, kWave * kStreamWaves, 0) !=
                 hipSuccess || v <= 0)
             v = 1;
         cached[dev] = v;
@@ -886,8 +900,14 @@ static int launch_stream_solve(const double* x, const double* y, int64_t n, doub
     // (default write-back stores: each store instruction here writes 64
     // scattered results, which written-through stores send to memory as
     // partial lines)
-    solve_stream_kernel<CH><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
-                                                                             nseg, chunks);
+    // 16-byte loads where x and y allow them
+    const bool vec = (CH % 2 == 0) && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    if (vec)
+        solve_stream_kernel<CH, true><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
+                                                                                          status, nseg, chunks);
+    else
+        solve_stream_kernel<CH, false><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
+                                                                                           status, nseg, chunks);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 

@@ -79,6 +79,26 @@ def test_stream_wide_intervals(gap):
     check(x, y, -1.0, 1.0, n, "gap %g" % gap)
 
 
+def test_stream_unaligned_inputs():
+    # knots and values that start 8 bytes past a 16-byte boundary take the
+    # 8-byte loads (aligned ones take 16-byte loads); the same results
+    n, m = (1 << 18) + 5, 300000
+    x, y = w.paper_curve(np.random.default_rng(77), n + 1)
+    xd, yd = dev(x), dev(y)
+    ypp = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    assert xd[1:].data_ptr() % 16 == 8
+    api.spline_solve_uniform(xd[1:], yd[1:], 0.5, -0.5, m, yq, ypp, st)
+    o_yq, o_ypp = oracle.spline_uniform(x[1:], y[1:], 0.5, -0.5, m)
+    assert int(host(st)[0]) == api.OK
+    assert_close(host(ypp), o_ypp, "unaligned ypp")
+    assert_close(host(yq), o_yq, "unaligned yq")
+    g_yq, g_ypp, _ = run(x[1:], y[1:], 0.5, -0.5, m)
+    np.testing.assert_array_equal(g_yq, host(yq))
+    np.testing.assert_array_equal(g_ypp, host(ypp))
+
+
 @pytest.mark.parametrize("n,m", [(1 << 26, 1 << 26), (1 << 28, 1 << 28)])
 def test_stream_full_size_sampled(n, m):
     # the size sweep's large points (m = n): every y'' and a sample of the
