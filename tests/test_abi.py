@@ -50,6 +50,7 @@ def test_constants_match_header():
     assert int(defs["SOLVE_E_TICKET"]) == api.E_TICKET
     assert int(defs["SOLVE_E_STATE"]) == api.E_STATE
     assert int(defs["SOLVE_MAX_N_BLOCK"]) == api.MAX_N_BLOCK
+    assert int(defs["SOLVE_MAX_N_SOLVE"]) == api.MAX_N_SOLVE
     assert int(defs["SOLVE_MAX_N_BATCH"]) == api.MAX_N_BATCH
     assert int(defs["SOLVE_PLAIN"].rstrip("u")) == api.PLAIN
 
@@ -60,6 +61,13 @@ def test_argument_errors_need_no_device(lib):
     assert lib.spline_build(p, p, 2, 0.0, 0.0, p, None, None) == api.E_SIZE
     assert lib.spline_build(p, p, api.MAX_N_BLOCK + 1, 0.0, 0.0, p, None, None) == api.E_SIZE
     assert lib.spline_eval_uniform(p, p, p, 10, 0, p, None) == api.E_SIZE
+    assert lib.spline_solve_uniform(p, None, 10, 0.0, 0.0, 5, p, None, None, None) == api.E_ARG
+    assert lib.spline_solve_uniform(p, p, 10, 0.0, 0.0, 5, None, p, None, None) == api.E_ARG
+    assert lib.spline_solve_uniform(p, p, 2, 0.0, 0.0, 5, p, None, None, None) == api.E_SIZE
+    assert lib.spline_solve_uniform(p, p, 10, 0.0, 0.0, 0, p, None, None, None) == api.E_SIZE
+    assert lib.spline_solve_uniform(p, p, api.MAX_N_SOLVE + 1, 0.0, 0.0, 5, p, None, None, None) == api.E_SIZE
+    assert lib.spline_solve_uniform_variant(p, p, 2, 0.0, 0.0, 5, 0, p, None, None, None) == api.E_SIZE
+    assert lib.spline_solve_uniform_variant(p, p, 10, 0.0, 0.0, 5, 99, p, None, None, None) == api.E_ARG
     assert lib.spline_eval_uniform(p, None, p, 10, 5, p, None) == api.E_ARG
     assert lib.spline_bracket_uniform(p, 2, 5, p, None) == api.E_SIZE
     assert lib.spline_noop_uniform(None, 5, 5, p, None) == api.E_ARG
