@@ -641,7 +641,10 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
 //   1. wavefront 0 finds the halo before the block, wavefront 1 the halo
 //      after it (adaptive, as above); wavefront 2 finds the first query above
 //      each knot of the block (a5), wavefront 3 the intervals' 1/(b - a);
-//   2. wavefront 0 solves rows [rs, re) (a1-a4) into LDS;
+//   2. wavefront 0 solves rows [rs, re) (a1-a4) into LDS, while wavefront 1
+//      splits the block's queries among the wavefronts and finds the
+//      intervals of each part's first and last query (from the first
+//      queries alone);
 //   3. the y'' the block owns are written and every wavefront evaluates its
 //      part of the block's queries (a6), interval by interval.
 // ---------------------------------------------------------------------------
@@ -654,6 +657,8 @@ struct CoopSmem {
     double so[kWave * kWaveSpanCH + 2];
     double inv[kMaxWaveBK];
     int64_t kq[kMaxWaveBK + 1];  // kq[i]: first query above knot j0 + i (0 and m at the curve's ends)
+    int64_t wk[kCoopWaves][2];   // each wavefront's queries [k0, k1)
+    int wt[kCoopWaves][2];       // and the intervals of queries k0 and k1-1
     int rs, re;
 };
 
@@ -732,30 +737,46 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
                                                                           bx, nullptr, nullptr, SoloGroup{}, lane, by,
                                                                           sm.so);
         if (bad && status && lane == 0) atomicMin(status, kStatusOrder);
+    } else if (wid == 1) {
+        // each wavefront's part of the block's queries (a5: kq[0] .. kq[nbk])
+        // and the intervals of its first and last query, while the span is
+        // solved
+        const int64_t ka = sm.kq[0];
+        const int64_t len = max(sm.kq[nbk] - ka, (int64_t)0);
+        const int64_t parts = (int64_t)shares * kCoopWaves;
+        int64_t per, rem;
+        if (len < 0x7fffffffLL && parts < 0x7fffffffLL) {  // 32-bit division where it fits
+            per = (uint32_t)len / (uint32_t)parts;
+            rem = (uint32_t)len - (uint32_t)per * (uint32_t)parts;
+        } else {
+            per = len / parts;
+            rem = len % parts;
+        }
+        for (int w = 0; w < kCoopWaves; ++w) {
+            const int64_t p = (int64_t)sh * kCoopWaves + w;
+            const int64_t k0 = ka + per * p + min(p, rem);
+            const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
+            int t0 = j0, t1 = j0;
+            if (k0 < k1) kq_span(sm.kq, j0, j1, k0, k1, lane, &t0, &t1);
+            if (lane == 0) {
+                sm.wk[w][0] = k0;
+                sm.wk[w][1] = k1;
+                sm.wt[w][0] = t0;
+                sm.wt[w][1] = t1;
+            }
+        }
     }
     __syncthreads();
     if (ypp && sh == 0) {
         const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
         for (int j = j0 + tid; j < jend; j += kCoopThreads) ypp[j] = sm.so[j - rs];
     }
-    // 3. this wavefront's part of the block's queries (a5: kq[0] .. kq[nbk])
-    const int64_t ka = sm.kq[0];
-    const int64_t len = max(sm.kq[nbk] - ka, (int64_t)0);
-    const int64_t parts = (int64_t)shares * kCoopWaves;
-    const int64_t p = (int64_t)sh * kCoopWaves + wid;
-    int64_t per, rem;
-    if (len < 0x7fffffffLL && parts < 0x7fffffffLL) {  // 32-bit division where it fits
-        per = (uint32_t)len / (uint32_t)parts;
-        rem = (uint32_t)len - (uint32_t)per * (uint32_t)parts;
-    } else {
-        per = len / parts;
-        rem = len % parts;
-    }
-    const int64_t k0 = ka + per * p + min(p, rem);
-    const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
+    // 3. this wavefront's part of the block's queries
+    const int64_t k0 = sm.wk[wid][0];
+    const int64_t k1 = sm.wk[wid][1];
     if (k0 >= k1) return;
-    eval_block_kq<false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1, yq,
-                                      lane);
+    eval_block_kq<false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1,
+                                      sm.wt[wid][0], sm.wt[wid][1], yq, lane);
 }
 
 static int cu_count() {

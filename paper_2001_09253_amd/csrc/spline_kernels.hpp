@@ -1305,21 +1305,13 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
     }
 }
 
-// Queries k0 .. k1-1 of the block [j0, j1) (all inside it), by one
-// wavefront, with the block's knots and values staged at [j - lo], its y'' at
-// [i - rs], sinv[t - j0] = 1/(x_{t+1} - x_t), and kq[i] the first query above
-// knot j0 + i (kq[0] and kq[j1 - j0] the block's first query and end): query
-// k lies in interval t exactly when kq[t - j0] <= k < kq[t + 1 - j0], so the
-// intervals come from integer compares alone.  Many queries per interval:
-// interval by interval, its constants in registers, 64 queries per store,
-// two independent rows per iteration, loop bounds in scalar registers.  Few:
-// 64 consecutive queries at a time, each lane stepping from the wavefront's
-// current interval.  Query m-1 (x[n-1] itself) is patched at the end.
-template <bool MIXED, int VARIANT = kHoisted, bool WT = false>
-__device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy, const double* so,
-                                              const double* sinv, const int64_t* kq, int lo, int rs, int j0, int j1,
-                                              double x0, double xl, double h, int64_t m, int64_t k0, int64_t k1,
-                                              double* __restrict__ out, int lane) {
+// The intervals t0 and t1 of queries k0 and k1-1 (k0 < k1) of the block
+// [j0, j1), with kq[i] the first query above knot j0 + i (kq[0] and
+// kq[j1 - j0] the block's first query and end): query k lies in interval t
+// exactly when kq[t - j0] <= k < kq[t + 1 - j0], so integer compares over the
+// block's interior knots give them.  Every lane receives both.
+__device__ __forceinline__ void kq_span(const int64_t* kq, int j0, int j1, int64_t k0, int64_t k1, int lane, int* t0,
+                                        int* t1) {
     const int nbk = j1 - j0;
     int ca = 0, cb = 0;
     for (int i = 1 + lane; i - lane < nbk; i += kWave) {  // interior knots of the block
@@ -1328,8 +1320,24 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
         ca += __popcll(__ballot(in && v <= k0));
         cb += __popcll(__ballot(in && v <= k1 - 1));
     }
-    const int t0 = j0 + ca;
-    const int t1 = j0 + cb;
+    *t0 = j0 + ca;
+    *t1 = j0 + cb;
+}
+
+// Queries k0 .. k1-1 of the block [j0, j1) (all inside it), by one
+// wavefront, with the block's knots and values staged at [j - lo], its y'' at
+// [i - rs], sinv[t - j0] = 1/(x_{t+1} - x_t), kq as for kq_span, and t0, t1
+// the intervals of queries k0 and k1-1 (kq_span).  Many queries per
+// interval: interval by interval, its constants in registers, 64 queries per
+// store, two independent rows per iteration, loop bounds in scalar
+// registers.  Few: 64 consecutive queries at a time, each lane stepping from
+// the wavefront's current interval.  Query m-1 (x[n-1] itself) is patched at
+// the end.
+template <bool MIXED, int VARIANT = kHoisted, bool WT = false>
+__device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy, const double* so,
+                                              const double* sinv, const int64_t* kq, int lo, int rs, int j0, int j1,
+                                              double x0, double xl, double h, int64_t m, int64_t k0, int64_t k1,
+                                              int t0, int t1, double* __restrict__ out, int lane) {
     const int nt = t1 - t0 + 1;
     if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
         const double kl0 = (double)k0 + (double)lane;
