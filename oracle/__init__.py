@@ -65,6 +65,8 @@ def lib():
                 "oracle_bracket_uniform": (C.c_int, [_d, C.c_int64, C.c_int64, _i64]),
                 "oracle_spline_uniform": (C.c_int, [_d, _d, C.c_int64, C.c_double, C.c_double,
                                                     C.c_int64, _d, _d]),
+                "oracle_uniform_range": (C.c_int, [_d, _d, _d, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                                   _d, _i64, C.c_int]),
                 "oracle_spline_uniform_sample": (C.c_int, [_d, _d, C.c_int64, C.c_double, C.c_double,
                                                            C.c_int64, _i64, C.c_int64, _d, _d]),
                 "oracle_batch_uniform": (C.c_int, [C.c_int64, _i64, _i64, _d, _d, _d, _d, _d, _d,
@@ -129,6 +131,11 @@ def second_derivatives(x, y, start_deriv, end_deriv):
     return out
 
 
+def uniform_query(x0, xlast, m, k):
+    """Position of uniform query k of m (one query)."""
+    return float(lib().oracle_uniform_query(float(x0), float(xlast), int(m), int(k)))
+
+
 def uniform_queries(x0, xlast, m):
     q = np.zeros(int(m))
     lib().oracle_uniform_queries(float(x0), float(xlast), int(m), _p(q))
@@ -181,6 +188,17 @@ def spline_uniform(x, y, start_deriv, end_deriv, m):
     _check(lib().oracle_spline_uniform(_p(x), _p(y), len(x), float(start_deriv), float(end_deriv),
                                        int(m), _p(yq), _p(ypp)))
     return yq, ypp
+
+
+def uniform_range(x, y, ypp, m, k0, k1, threads: int = 0):
+    """(values, intervals) of uniform queries k0..k1-1 of m, given ypp[n]."""
+    x, y, ypp = _f64(x), _f64(y), _f64(ypp)
+    cnt = int(k1) - int(k0)
+    yq = np.zeros(max(cnt, 0))
+    idx = np.zeros(max(cnt, 0), dtype=np.int64)
+    _check(lib().oracle_uniform_range(_p(x), _p(y), _p(ypp), len(x), int(m), int(k0), int(k1), _p(yq),
+                                      _p(idx, _i64), int(threads)))
+    return yq, idx
 
 
 def spline_uniform_sample(x, y, start_deriv, end_deriv, m, ks):

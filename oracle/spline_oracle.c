@@ -299,6 +299,34 @@ int oracle_spline_uniform(const double *x, const double *y, int64_t n, double st
     return rc;
 }
 
+/*
+ * Uniform queries k0 .. k1-1 of m (reading A5) on a curve whose second
+ * derivatives ypp are given: yq[k - k0] is the value at query k and, when idx
+ * is not NULL, idx[k - k0] its interval.  Each query is positioned, bracketed
+ * and evaluated on its own exactly as in oracle_spline_uniform; the queries
+ * are spread over `threads` OpenMP threads (<= 0: the OpenMP default), which
+ * changes no arithmetic.  Lets a caller check a long run of queries chunk by
+ * chunk.
+ */
+int oracle_uniform_range(const double *x, const double *y, const double *ypp, int64_t n, int64_t m,
+                         int64_t k0, int64_t k1, double *yq, int64_t *idx, int threads)
+{
+    if (n < 2 || m < 1 || k0 < 0 || k1 > m || k0 > k1 || !x || !y || !ypp || !yq) return ORACLE_E_ARG;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+#else
+    (void)threads;
+#endif
+    for (int64_t k = k0; k < k1; ++k) {
+        double q = oracle_uniform_query(x[0], x[n - 1], m, k);
+        int64_t i = oracle_bracket(x, n, q);
+        if (idx) idx[k - k0] = i;
+        yq[k - k0] = oracle_eval_interval(x, y, ypp, i, q);
+    }
+    return ORACLE_OK;
+}
+
 /* Only a sample of the uniform queries: yq[r] = value at query index ks[r]. */
 int oracle_spline_uniform_sample(const double *x, const double *y, int64_t n, double start_deriv,
                                  double end_deriv, int64_t m, const int64_t *ks, int64_t count,

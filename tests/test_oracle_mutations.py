@@ -36,6 +36,7 @@ MUTATIONS = {
     "elim_sign": ("r[k + 1] -= l * r[k];", "r[k + 1] += l * r[k];"),
     "backsub_drop_fill": ("out[k] = (r[k] - f1[k] * out[k + 1] - f2[k] * out[k + 2]) / dg[k];",
                           "out[k] = (r[k] - f1[k] * out[k + 1]) / dg[k];"),
+    "query_fused": ("double step = (double)k * h;\n    return x0 + step;", "return fma((double)k, h, x0);"),
     "query_step": ("double h = (xlast - x0) / (double)(m - 1);", "double h = (xlast - x0) / (double)m;"),
     "sentinel_not_strict": ("return deriv > 0.99e30;", "return deriv >= 0.99e30;"),
     "eval_C_factor": ("double C = (A * A * A - A) * (h * h) / 6.0;", "double C = (A * A * A - A) * (h * h) / 3.0;"),
@@ -93,11 +94,13 @@ def _battery(L):
         s = np.max(np.abs(t_ypp)) + 1.0
         if rc or np.max(np.abs(ypp - t_ypp)) > 1e-12 * s or np.max(np.abs(yq - t_yq)) > 1e-12 * s:
             failed.append("exact:%d" % seed)
-    # uniform queries: end points and spacing
-    q = np.zeros(11)
-    L.oracle_uniform_queries(0.0, 1.0, 11, _p(q))
-    if q[-1] != 1.0 or np.max(np.abs(q - np.linspace(0, 1, 11))) > 1e-15:
-        failed.append("queries")
+    # uniform queries: the bits of np.linspace, the paper's sampling call
+    for x0, x1, m in ((0.0, 1.0, 11), (0.1, 1e6, 100003), (-7.5, -0.25, 65537)):
+        q = np.zeros(m)
+        L.oracle_uniform_queries(x0, x1, m, _p(q))
+        if not np.array_equal(q, np.linspace(x0, x1, m)):
+            failed.append("queries")
+            break
     # bracketing against the paper's scan loop, queries placed on the knots
     x = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
     idx = np.zeros(9, dtype=np.int64)

@@ -95,6 +95,17 @@ def test_exact_rational_spline(seed):
     assert np.max(np.abs(yq - tv)) <= 1e-13 * (np.max(np.abs(tv)) + scale * (x[-1] - x[0]) ** 2)
 
 
+@pytest.mark.parametrize("n", [24, 40])
+def test_exact_rational_spline_longer(n):
+    # two longer curves (the rational solve grows as n^3: n = 40 takes seconds)
+    x, y = _rand_curve(500 + n, n)
+    for sd, ed in (BCS[0], BCS[2]):
+        ex = ExactSpline(x, y, sd, ed)
+        truth = np.array([float(v) for v in ex.second_derivatives()])
+        ypp = oracle.second_derivatives(x, y, sd, ed)
+        assert np.max(np.abs(ypp - truth)) <= 1e-13 * (np.max(np.abs(truth)) + 1e-300)
+
+
 def test_exact_rational_wild_spacing():
     # intervals from 1e-9 to 1e3 in one curve
     x = np.array([0.0, 1e-9, 1.0, 1.0 + 1e-6, 1000.0, 1000.5, 2000.0])
@@ -267,15 +278,34 @@ def test_bracket_matches_scan(seed):
         assert i == min(max(cnt - 1, 0), n - 2)
 
 
-def test_uniform_queries():
-    for x0, x1, m in [(0.0, 2.5, 2048), (-3.0, 7.25, 1), (1.0, 2.0, 2), (0.1, 1e6, 100003)]:
-        q = oracle.uniform_queries(x0, x1, m)
-        assert q[0] == x0
-        if m > 1:
-            assert q[-1] == x1
-            assert np.all(np.diff(q) >= 0)
-            ref = np.linspace(x0, x1, m)
-            assert np.max(np.abs(q - ref)) <= 4 * np.spacing(max(abs(x0), abs(x1)))
+# (x0, x_last, m): the worked size, m = 1 and 2, wide and narrow ranges, a
+# negative range, and C2's 2,048,000 queries
+QUERY_CASES = [(0.0, 2.5, 2048), (-3.0, 7.25, 1), (1.0, 2.0, 2), (0.1, 1e6, 100003), (0.0, 13.0, 2048),
+               (-1e-3, 5e5, 2048000), (3.7, 3.7000001, 999), (-7.5, -0.25, 65537), (0.0, 1.0, 11)]
+
+
+@pytest.mark.parametrize("x0,x1,m", QUERY_CASES)
+def test_uniform_queries_are_linspace_bit_for_bit(x0, x1, m):
+    # The paper samples its interpolated curve with np.linspace(min, max,
+    # 2048) ("Quality Checks"); the oracle's positions must be those bits
+    # exactly (one multiply, then one add, never fused; the last query is
+    # x_last itself), since the bracketing of on-knot queries depends on them.
+    q = oracle.uniform_queries(x0, x1, m)
+    np.testing.assert_array_equal(q, np.linspace(x0, x1, m))
+    assert q[0] == x0
+    if m > 1:
+        assert q[-1] == x1
+        assert np.all(np.diff(q) >= 0)
+    for k in {0, 1, m // 2, m - 2, m - 1}:
+        if 0 <= k < m:
+            assert oracle.uniform_query(x0, x1, m, k) == q[k]
+
+
+def test_uniform_queries_of_the_worked_example():
+    # the worked example's own call: 2048 points between the first and last
+    # of the 13 hand knots
+    q = oracle.uniform_queries(w.HAND_KNOTS[0], w.HAND_KNOTS[-1], 2048)
+    np.testing.assert_array_equal(q, np.linspace(min(w.HAND_KNOTS), max(w.HAND_KNOTS), 2048))
 
 
 def test_validation_codes():
