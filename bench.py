@@ -9,15 +9,19 @@ query evaluation, so a pass over a curve with n knots and m queries is n + m
 steps.  Inputs are resident in HBM before the timed region starts.
 
 Workloads (--workload):
-  plain    (default) 1 curve, n = 13,000 knots, m = 2,048,000 uniform queries
-           (the paper's 13-knot / 2048-point worked size scaled 1000x), seed 0
+  batched  (default) 4096 curves, sizes log-uniform 0.1x..10x of the worked
+           size (13 knots, 2048 queries), seed 0: one launch per step over
+           autotuned work items, the outputs rotated over >= 2 GiB so that
+           they go to HBM; beside it (unless --no-context) the single-curve
+           kernel on C2 and C2x and a short served run against the plain path
+  plain    1 curve, n = 13,000 knots, m = 2,048,000 uniform queries (the
+           paper's 13-knot / 2048-point worked size scaled 1000x), seed 0
   small    1 curve, n = 13, m = 2048 (the worked size itself)
   plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
+  points   1 curve, n = 13,000, m = 2^27 explicit queries (random, or
+           --sorted), with first and second derivatives (spline_eval_points)
   long     1 curve, n = m = 2^28 (the size sweep's largest point: one query
            per interval, the streaming kernel)
-  batched  4096 curves, sizes log-uniform 0.1x..10x of the worked size, one
-           launch per step over autotuned work items (timed as a hipGraph
-           replay and as a direct launch; the faster gives the value)
   mixed    the batched workload with the FP32 solve + FP64 refinement
   served   Poisson arrivals at 2000 req/s (sizes 0.1x..100x) through the
            request API, continuous batching vs the plain one-request path
@@ -202,6 +206,35 @@ def cpu_baseline_single(inst, seconds):
             "ns_per_point": per / m * 1e9}
 
 
+def host_cpu():
+    """Logical CPUs this process may use and the CPU model name (from lscpu,
+    else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count() or 1
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return ncpu, model
+
+
 def bench_batched(args, precision):
     import numpy as np
     import torch
@@ -238,13 +271,13 @@ def bench_batched(args, precision):
         t1 = time.perf_counter()
         return e_begin.elapsed_time(e_end) / K, (t1 - t0) / K
 
-    # the step as a hipGraph replay, and as a direct launch of the plan
+    # context first: the step as a hipGraph replay and as a direct launch on
+    # the same output buffers (which then stay in the 256 MB last-level cache)
     replay_ms, replay_s = timed(lambda: api.spline_plan_replay(plan, stream=stream))
-    direct_ms, direct_s = timed(lambda: api.spline_plan_run(plan, bufs, stream=stream))
-    step_s = min(replay_s, direct_s)
-    launch_ms = direct_ms  # the plan's kernels alone, launched back to back
-    # outputs rotated over >= 2 GiB, so that no launch finds its outputs in
-    # the 256 MB last-level cache
+    warm_ms, warm_s = timed(lambda: api.spline_plan_run(plan, bufs, stream=stream))
+    # the measured steps, last: direct launches with the outputs rotated over
+    # >= 2 GiB, so that no launch finds its outputs in the last-level cache
+    # (the results go to HBM, as a job larger than the cache would send them)
     out_bytes = 8 * (int(b.qoff[-1]) + int(b.koff[-1]))
     nrot = max(2, -(-(2 << 30) // out_bytes))
     rot = [dict(bufs, yq=torch.empty_like(bufs["yq"]), ypp=torch.empty_like(bufs["ypp"])) for _ in range(nrot)]
@@ -253,35 +286,43 @@ def bench_batched(args, precision):
     def rotated():
         api.spline_plan_run(plan, rot[it[0] % nrot], stream=stream)
         it[0] += 1
-    rot_ms, _ = timed(rotated)
+    rot_ms, rot_s = timed(rotated)
     del rot
     N, M = int(b.koff[-1]), int(b.qoff[-1])
-    value = (N + M) / step_s
+    value = (N + M) / rot_s
+    # algorithmic bytes per launch: read x, y (16 per knot), write y'' (8 per
+    # knot) and the results (8 per query), and per curve its two end
+    # derivatives and two offsets (8 each) and its 48-byte work item
     dbytes = 24.0 * N + 8.0 * M + 16.0 * b.count * 2 + 8.0 * b.count * 2
-    achieved = dbytes / (launch_ms * 1e-3) / 1e9
+    achieved = dbytes / (rot_ms * 1e-3) / 1e9
     wl = "batched" if precision == api.FP64 else "mixed"
+    kern = "coop_items" if best.fused == 3 else "wave_items"
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
-        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": rot_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if precision == api.FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": wl, "instances": b.count, "sum_n": N, "sum_m": M,
-                   "sizes": "log-uniform 0.1x..10x of (13, 2048)", "ends": "natural/flat/twist cycle", "seed": 0,
+        "config": {"workload": "%s: 4096 curves, sizes log-uniform 0.1x..10x of (13 knots, 2048 queries), one "
+                               "launch per step, outputs rotated over %.1f GB" % (wl, nrot * out_bytes / 1e9),
+                   "instances": b.count, "sum_n": N, "sum_m": M, "ends": "natural/flat/twist cycle", "seed": 0,
+                   "generator": "x_j = x_{j-1} + U(0,1) (0 -> 1e-4), y_j = U(0,1)",
                    "tuning": {"block": best.block, "queries_per_tile": best.queries_per_tile,
                               "grid_per_cu": best.grid_per_cu, "fused": best.fused}},
-        "roofline": {"bound": "hbm", "kernel": "coop_items" if best.fused == 3 else "wave_items",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("coop_items" if best.fused == 3 else "wave_items", wl),
-                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": launch_ms},
-        "step_ms": {"graph_replay": replay_ms, "direct_launch": direct_ms,
-                    "host_graph_replay": replay_s * 1e3, "host_direct_launch": direct_s * 1e3,
-                    "direct_launch_outputs_rotated": rot_ms},
-        "rotated_outputs": {"buffers": nrot, "bytes": nrot * out_bytes, "avg_launch_ms": rot_ms,
-                            "frac": dbytes / (rot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kern, wl),
+                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": rot_ms},
+        "step_ms": {"outputs_rotated": rot_ms, "host_outputs_rotated": rot_s * 1e3,
+                    "outputs_in_cache": warm_ms, "host_outputs_in_cache": warm_s * 1e3,
+                    "graph_replay_outputs_in_cache": replay_ms, "host_graph_replay": replay_s * 1e3},
+        "outputs_in_cache": {"frac": dbytes / (warm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "note": "the same launch with its outputs left in the last-level cache"},
+        "rotated_outputs": {"buffers": nrot, "bytes": nrot * out_bytes},
     }
     if precision != api.FP64:
         # per-instance error of the mixed path against the FP64 oracle, in
         # the scaled metric |g - o| / (|o| + max|o| of the instance)
         import oracle
+        api.spline_plan_run(plan, bufs, stream=stream)
+        stream.synchronize()
         o_yq, o_ypp, _, _ = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
         yq = bufs["yq"].cpu().numpy()
         ypp = bufs["ypp"].cpu().numpy()
@@ -300,23 +341,156 @@ def bench_batched(args, precision):
                     "p99": float(np.percentile(e_ypp, 99))}}
     if not args.no_cpu_baseline:
         import oracle
-        sub = 512
-        koff = b.koff[:sub + 1]
-        qoff = b.qoff[:sub + 1]
+        # the oracle over the whole batch (all 4096 curves), OpenMP over
+        # curves on the host's cores, repeated for about --cpu-seconds
+        ncpu, model = host_cpu()
         t0 = oracle.now()
         reps = 0
         used = 1
         while True:
-            _, _, _, used = oracle.batch_uniform(koff, qoff, b.x[:koff[-1]], b.y[:koff[-1]], b.sd[:sub], b.ed[:sub])
+            _, _, _, used = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
             reps += 1
             if oracle.now() - t0 >= args.cpu_seconds:
                 break
         t = oracle.now() - t0
-        steps = (int(koff[-1]) + int(qoff[-1])) * reps
-        out["cpu_baseline"] = {"value": steps / t, "unit": UNIT, "cores": used, "kind": "oracle",
-                               "sample": "first %d of the 4096 curves, %d repetitions in %.1f s, OpenMP over curves"
-                                         % (sub, reps, t)}
+        out["cpu_baseline"] = {"value": (N + M) * reps / t, "unit": UNIT, "cores": used, "kind": "oracle",
+                               "sample": "the whole batch (all %d curves), %d repetitions in %.1f s, OpenMP over "
+                                         "curves on %d threads" % (b.count, reps, t, used),
+                               "nproc": ncpu, "cpu_model": model, "ms_per_step": t / reps * 1e3}
     return out
+
+
+def bench_points(args, sorted_queries):
+    """Explicit queries at scale: one curve of 13,000 knots and 2^27 query
+    points drawn uniformly over its range (in random order, or sorted), each
+    bracketed by search and evaluated with its first and second derivative.
+    A step is the build (y'' of the curve) plus the evaluation of every
+    point."""
+    import numpy as np
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    n, m = 13000, 1 << 27
+    inst = workloads.single(0, n, m, bc=0)
+    rng = np.random.default_rng(1)
+    xq_h = rng.uniform(inst.x[0], inst.x[-1], m)
+    x = torch.from_numpy(inst.x).cuda()
+    y = torch.from_numpy(inst.y).cuda()
+    xq = torch.from_numpy(xq_h).cuda()
+    if sorted_queries:
+        xq = torch.sort(xq).values.contiguous()
+    ypp = torch.empty_like(x)
+    one = torch.empty(1, dtype=torch.float64, device="cuda")
+    yq = torch.empty(m, dtype=torch.float64, device="cuda")
+    d1 = torch.empty_like(yq)
+    d2 = torch.empty_like(yq)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    sd, ed = inst.start_deriv, inst.end_deriv
+    K = args.steps
+
+    def build():  # y'' of the curve (the single-launch kernel, one throw-away query)
+        api.spline_solve_uniform(x, y, sd, ed, 1, one, ypp, stream=sp)
+
+    def evaluate(derivs):
+        api.spline_eval_points(x, y, ypp, xq, yq, d1 if derivs else None, d2 if derivs else None, stream=sp)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(K):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K, (time.perf_counter() - t0) / K
+
+    build_ms, _ = timed(build)
+    vals_ms, _ = timed(lambda: evaluate(False))
+    eval_ms, _ = timed(lambda: evaluate(True))
+    step_ms, step_s = timed(lambda: (build(), evaluate(True)))
+    # algorithmic bytes of the evaluation launch: read the points (8 per
+    # query), write value, first and second derivative (24 per query), read
+    # x, y and y'' (24 per knot)
+    dbytes = 32.0 * m + 24.0 * n
+    achieved = dbytes / (eval_ms * 1e-3) / 1e9
+    wl = "points_sorted" if sorted_queries else "points"
+    out = {
+        "metric": METRIC, "value": (n + m) / step_s, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s: 1 curve, n=13000, m=2^27 explicit points (%s), value + first and second "
+                               "derivative" % (wl, "sorted" if sorted_queries else "random order"),
+                   "instances": 1, "n": n, "m": m, "ends": "natural", "seed": 0,
+                   "points": "U(x_0, x_{n-1}), numpy default_rng(1)"},
+        "roofline": {"bound": "hbm", "kernel": "eval_points", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("eval_points", wl),
+                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": eval_ms},
+        "kernels_ms": {"build": build_ms, "eval_points_values": vals_ms, "eval_points_with_derivatives": eval_ms,
+                       "step_event_ms": step_ms},
+        "values_only": {"ms": vals_ms, "frac": (16.0 * m + 24.0 * n) / (vals_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle, single thread, on the first 2^22 points (value and
+        # derivatives), repeated for about --cpu-seconds
+        k = 1 << 22
+        q = np.ascontiguousarray(np.sort(xq_h[:k]) if sorted_queries else xq_h[:k])
+        o_ypp = oracle.second_derivatives(inst.x, inst.y, sd, ed)
+        reps = 0
+        t0 = oracle.now()
+        while True:
+            oracle.eval_points(inst.x, inst.y, o_ypp, q)
+            oracle.eval_points_derivs(inst.x, inst.y, o_ypp, q)
+            reps += 1
+            if oracle.now() - t0 >= args.cpu_seconds:
+                break
+        t = oracle.now() - t0
+        out["cpu_baseline"] = {"value": k * reps / t, "unit": UNIT, "cores": 1, "kind": "oracle",
+                               "sample": "the first 2^22 points (%s), value and derivatives, %d repetitions in "
+                                         "%.1f s, single thread (the build of y'' not timed)"
+                                         % ("sorted" if sorted_queries else "random order", reps, t),
+                               "ns_per_point": t / (k * reps) * 1e9}
+    return out
+
+
+def plain_context(args):
+    """The single-curve configurations beside the batch: C2 (13,000 knots,
+    2,048,000 queries) in one launch, and the same curve at m = 2^27 (out of
+    the last-level cache), kernel time only."""
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    res = {}
+    for name, n, m in (("plain", 13000, 2048000), ("plain2x", 13000, 1 << 27)):
+        inst = workloads.single(0, n, m, bc=0)
+        x = torch.from_numpy(inst.x).cuda()
+        y = torch.from_numpy(inst.y).cuda()
+        ypp = torch.empty_like(x)
+        yq = torch.empty(m, dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        sp = stream.cuda_stream
+        reps = 200 if m < (1 << 24) else 20
+        for _ in range(5):
+            api.spline_solve_uniform(x, y, inst.start_deriv, inst.end_deriv, m, yq, ypp, stream=sp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            api.spline_solve_uniform(x, y, inst.start_deriv, inst.end_deriv, m, yq, ypp, stream=sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        b_alg = 24.0 * n + 8.0 * m
+        res[name] = {"n": n, "m": m, "ms": ms, "steps_per_s": (n + m) / (ms * 1e-3),
+                     "frac": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del x, y, ypp, yq
+    return res
 
 
 def bench_served(args):
@@ -409,6 +583,27 @@ def bench_served(args):
                                "sample": "first %d measured requests of the trace, back to back (no arrival "
                                          "gaps), OpenMP over requests, %.1f s" % (k, t)}
     return out
+
+
+def served_context(seconds, rate=2000.0):
+    """The served configuration, short: Poisson arrivals through the request
+    API, continuous batching against the plain single-instance path (the
+    same trace), latency from the scheduled arrival to the result."""
+    from paper_2001_09253_amd import api, serve, workloads
+
+    trace = workloads.poisson_trace(0, rate, seconds + 1.0, 0.1, 100.0)
+    reqs = serve.make_requests(trace, 1)
+    short = workloads.Trace(trace.t[:64] - trace.t[0], trace.n[:64], trace.m[:64])
+    serve.replay(short, reqs[:64])
+    serve.replay(short, reqs[:64], plain=True)
+    res_b, _ = serve.replay(trace, reqs, warmup_s=1.0, flags=api.NO_GRAPH)
+    res_p, _ = serve.replay(trace, reqs, plain=True, warmup_s=1.0)
+    sb, sp = res_b.summary(), res_p.summary()
+    return {"workload": "Poisson %.0f req/s for %.0f s after 1 s warm-up, sizes log-uniform 0.1x..100x of "
+                        "(13, 2048), host result buffers, 200 GB budget" % (rate, seconds),
+            "served_p50_ms": sb["p50_ms"], "served_p99_ms": sb["p99_ms"], "plain_p50_ms": sp["p50_ms"],
+            "plain_p99_ms": sp["p99_ms"], "served_steps_per_s": sb["steps_per_s"],
+            "plain_steps_per_s": sp["steps_per_s"], "requests": res_b.requests}
 
 
 def bench_sweep(args):
@@ -534,8 +729,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "plain2x", "long", "batched", "mixed", "served", "copy", "sweep"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["plain", "small", "plain2x", "points", "long", "batched", "mixed", "served", "copy",
+                             "sweep"])
+    ap.add_argument("--sorted", action="store_true", help="points: sorted query points")
     ap.add_argument("--variant", default=None,
                     choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul", "horner"],
                     help="single-curve workloads: time this evaluation formula on the one-launch kernel")
@@ -546,6 +743,10 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=200, help="served: HBM admission budget")
     ap.add_argument("--served-graph", action="store_true", help="served: capture each batch as a hipGraph")
     ap.add_argument("--sweep", action="store_true", help="served: also a short sweep of arrival rates")
+    ap.add_argument("--no-context", action="store_true",
+                    help="batched: skip the single-curve and served context measurements")
+    ap.add_argument("--context-seconds", type=float, default=4.0,
+                    help="batched: measured seconds of each served path in the context")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: the spline path is measured on one MI355X "
@@ -557,12 +758,19 @@ def main():
         out = bench_single(args, 13, 2048, "small: 1 curve, n=13, m=2048 uniform queries")
     elif args.workload == "plain2x":
         out = bench_single(args, 13000, 1 << 27, "plain2x: 1 curve, n=13000, m=2^27 uniform queries")
+    elif args.workload == "points":
+        out = bench_points(args, args.sorted)
     elif args.workload == "long":
         out = bench_single(args, 1 << 28, 1 << 28, "long: 1 curve, n=m=2^28 (the size sweep's largest point)",
                            cpu_sample=1 << 22)
     elif args.workload in ("batched", "mixed"):
         from paper_2001_09253_amd import api
         out = bench_batched(args, api.FP64 if args.workload == "batched" else api.FP32_REFINE)
+        if args.workload == "batched" and not args.no_context:
+            # beside the batch: the single-curve kernel on C2 and C2x, and the
+            # served form against the plain single-instance path
+            out["context"] = {"single_curve": plain_context(args),
+                              "served": served_context(args.context_seconds)}
     elif args.workload == "copy":
         out = bench_copy(args)
     elif args.workload == "sweep":

@@ -71,9 +71,10 @@ extern "C" {
 #define SOLVE_NO_GRAPH 2u     /* launch kernels directly instead of a hipGraph    */
 
 /* ---- limits ------------------------------------------------------------------- */
-#define SOLVE_MAX_N_BLOCK 16384   /* largest n one workgroup solves (plain path) */
+#define SOLVE_MAX_N_BLOCK 16384   /* largest n of spline_build (one workgroup)   */
 #define SOLVE_MAX_N_BATCH 2048    /* largest n of an instance in a fused batch   */
-#define SOLVE_MAX_N_SOLVE 1073741824  /* largest n of spline_solve_uniform (2^30) */
+#define SOLVE_MAX_N_SOLVE 1073741824  /* largest n of spline_solve_uniform and of a */
+                                      /* request (2^30)                            */
 
 typedef struct solve_ctx solve_ctx;
 typedef uint64_t solve_ticket;
@@ -85,7 +86,10 @@ typedef struct {
     uint32_t precision;        /* SOLVE_FP64 or SOLVE_FP32_REFINE                    */
     uint32_t flags;            /* SOLVE_PLAIN, SOLVE_NO_GRAPH                        */
     uint32_t max_inflight;     /* batches in flight on the device (>= 1; 0 = 2)     */
-    void *stream;              /* optional hipStream_t for the compute work         */
+    void *stream;              /* the caller's hipStream_t (NULL = the legacy        */
+                               /* default stream): solve_submit orders its reads of */
+                               /* device inputs and writes of device outputs after  */
+                               /* the work queued there when it is called           */
 } solve_config;
 
 /* ============================================================================
@@ -104,20 +108,25 @@ int solve_create(const solve_config *cfg, solve_ctx **out);
 
 /* Submit one curve.  knots/values: n doubles each (host or device pointers,
  * detected per pointer); they are copied before the call returns, so the
- * caller may free them at once.  start_deriv/end_deriv: see the conventions.
- * xq: m explicit query points, or NULL for m uniform queries.  yq_out: m
- * results, ypp_out: n second derivatives or NULL; both caller-owned, device,
- * pinned host (written by the device directly) or pageable host (copied from
- * the library's pinned staging), and written only when the request completes
- * -- they must stay valid until solve_poll reports DONE/ERROR or until
- * solve_destroy.  *ticket_out
+ * caller may free them at once.  Device inputs are read after the work queued
+ * on cfg->stream when the call is made (so a kernel that produces them there
+ * just before the call is waited for).  start_deriv/end_deriv: see the
+ * conventions.  xq: m explicit query points, or NULL for m uniform queries.
+ * yq_out: m results, ypp_out: n second derivatives or NULL; both
+ * caller-owned, device, pinned host (written by the device directly) or
+ * pageable host (copied from the library's pinned staging), and written only
+ * when the request completes -- they must stay valid until solve_poll reports
+ * DONE/ERROR or until solve_destroy.  Device outputs are written after the
+ * work queued on cfg->stream when the call is made.  Curves of up to
+ * SOLVE_MAX_N_BATCH knots join the fused batches; longer ones (and every
+ * SOLVE_PLAIN request) run on the kernels of spline_solve_uniform (with
+ * explicit queries: its y'' and then spline_eval_points).  *ticket_out
  * receives the request's ticket.  Errors: E_ARG, E_SIZE (n < 3, m < 1,
- * n > SOLVE_MAX_N_BATCH without SOLVE_PLAIN, n > SOLVE_MAX_N_BLOCK), E_ORDER
- * (the copied knots are checked before the call returns), E_BUDGET (the
- * request's resident footprint 8*(3n + m [+ m for explicit queries]) + 64
- * bytes exceeds hbm_budget_bytes), E_STATE (context shutting down),
- * E_DEVICE.  With SOLVE_PLAIN the request has completed when the call
- * returns (its ticket then polls DONE or ERROR). */
+ * n > SOLVE_MAX_N_SOLVE), E_ORDER (the copied knots are checked before the
+ * call returns), E_BUDGET (the request's resident footprint 8*(3n + m [+ m for
+ * explicit queries]) + 64 bytes exceeds hbm_budget_bytes), E_STATE (context
+ * shutting down), E_DEVICE.  With SOLVE_PLAIN the request has completed when
+ * the call returns (its ticket then polls DONE or ERROR). */
 int solve_submit(solve_ctx *ctx, const double *knots, const double *values, int64_t n,
                  double start_deriv, double end_deriv, const double *xq, int64_t m,
                  double *yq_out, double *ypp_out, solve_ticket *ticket_out);
@@ -198,6 +207,17 @@ int spline_eval_uniform(const double *x, const double *y, const double *ypp, int
 int spline_solve_uniform(const double *x, const double *y, int64_t n, double start_deriv,
                          double end_deriv, int64_t m, double *yq, double *ypp, int32_t *status,
                          void *stream);
+
+/* spline_solve_uniform that also reports step a5's result: idx[k] (m device
+ * int32, output) receives the interval of uniform query k, clip(#{j : x_j <
+ * q_k} - 1, 0, n-2), as each kernel decided it.  It runs the same kernels,
+ * chosen by the same rule, compiled with one more store per result, so that
+ * the bracketing of the path spline_solve_uniform runs can be checked exactly;
+ * yq, ypp and status are as for spline_solve_uniform (and bit-identical to
+ * it).  Errors: E_ARG (also idx NULL), E_SIZE as spline_solve_uniform. */
+int spline_solve_uniform_indexed(const double *x, const double *y, int64_t n, double start_deriv,
+                                 double end_deriv, int64_t m, double *yq, double *ypp, int32_t *idx,
+                                 int32_t *status, void *stream);
 
 /* The per-query formulas compared in the paper's "Benchmarks" section
  * ("Curve Interpolation": newint, newint__orig, newint__noinv, splint_one__div,
@@ -295,6 +315,15 @@ int spline_plan_create(int device, int64_t count, const int64_t *koff, const int
 int spline_plan_run(spline_plan *plan, const double *x, const double *y, const double *sd,
                     const double *ed, const int64_t *koff, const int64_t *qoff, double *yq,
                     double *ypp, int32_t *status, void *stream);
+
+/* spline_plan_run that also writes the interval of every query: idx (sum m
+ * device int32, output, CSR like yq) receives, for query k of curve i,
+ * clip(#{j : x_j < q_k} - 1, 0, n_i - 2), counted within curve i.  The same
+ * kernels compiled with one more store per result (yq, ypp and status as
+ * spline_plan_run).  Errors: E_ARG (also idx NULL). */
+int spline_plan_run_indexed(spline_plan *plan, const double *x, const double *y, const double *sd,
+                            const double *ed, const int64_t *koff, const int64_t *qoff, double *yq,
+                            double *ypp, int32_t *idx, int32_t *status, void *stream);
 
 /* Capture one spline_plan_run with these pointers into a hipGraph owned by
  * the plan; spline_plan_replay then launches that graph on `stream`. */

@@ -47,6 +47,7 @@ SIGNATURES = {
     "solve_destroy": (C.c_int, [_vp]),
     "spline_build": (C.c_int, [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp]),
     "spline_solve_uniform": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _vp, _vp, _vp, _vp]),
+    "spline_solve_uniform_indexed": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _vp, _vp, _vp, _vp, _vp]),
     "spline_solve_uniform_variant": (C.c_int, [_vp, _vp, _i64, _d, _d, _i64, _i32, _vp, _vp, _vp, _vp]),
     "spline_eval_uniform": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
     "spline_bracket_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),
@@ -54,6 +55,7 @@ SIGNATURES = {
     "spline_eval_points": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "spline_plan_create": (C.c_int, [C.c_int, _i64, _vp, _vp, _u32, C.POINTER(Tuning), C.POINTER(_vp)]),
     "spline_plan_run": (C.c_int, [_vp] + [_vp] * 10),
+    "spline_plan_run_indexed": (C.c_int, [_vp] + [_vp] * 11),
     "spline_plan_capture": (C.c_int, [_vp] + [_vp] * 10),
     "spline_plan_replay": (C.c_int, [_vp, _vp]),
     "spline_plan_autotune": (C.c_int, [_vp] + [_vp] * 8 + [C.c_int, C.c_char_p, C.POINTER(Tuning),

@@ -101,6 +101,17 @@ def spline_solve_uniform(x, y, start_deriv, end_deriv, m, yq, ypp=None, status=N
            "spline_solve_uniform")
 
 
+def spline_solve_uniform_indexed(x, y, start_deriv, end_deriv, m, yq, idx, ypp=None, status=None, stream=None):
+    """spline_solve_uniform that also writes every query's interval into idx
+    (int32, m)."""
+    n = x.numel()
+    _check(_native.lib().spline_solve_uniform_indexed(
+        _dev(x, name="x"), _dev(y, name="y", numel=n), n, float(start_deriv), float(end_deriv), int(m),
+        _dev(yq, name="yq", numel=int(m)), _dev(ypp, name="ypp", numel=n, optional=True),
+        _dev(idx, torch.int32, "idx", int(m)), _dev(status, torch.int32, "status", 1, optional=True),
+        _stream(stream)), "spline_solve_uniform_indexed")
+
+
 # evaluation formulas of spline_solve_uniform_variant (the paper's
 # "Curve Interpolation" benchmark variants)
 NEWINT_HOISTED = 0
@@ -200,6 +211,15 @@ def spline_plan_run(plan, bufs, status=None, stream=None):
     _check(_native.lib().spline_plan_run(plan.handle, *_plan_args(plan, bufs),
                                          _dev(status, torch.int32, "status", plan.count, optional=True),
                                          _stream(stream)), "spline_plan_run")
+
+
+def spline_plan_run_indexed(plan, bufs, idx, status=None, stream=None):
+    """spline_plan_run that also writes every query's interval (within its
+    curve) into idx (int32, sum m)."""
+    _check(_native.lib().spline_plan_run_indexed(plan.handle, *_plan_args(plan, bufs),
+                                                 _dev(idx, torch.int32, "idx", int(plan.qoff[-1])),
+                                                 _dev(status, torch.int32, "status", plan.count, optional=True),
+                                                 _stream(stream)), "spline_plan_run_indexed")
 
 
 def spline_plan_capture(plan, bufs, status=None, stream=None):

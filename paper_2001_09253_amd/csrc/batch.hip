@@ -210,7 +210,7 @@ __device__ __forceinline__ bool build_any(const double* __restrict__ x, const do
 // One wave item.  All 64 lanes of the wavefront call this.  BUILD: items of
 // curves past a.prebuilt_max_n knots solve their span here; curves up to that
 // length were built by phase 1.
-template <int CH, bool BUILD, bool MIXED>
+template <int CH, bool BUILD, bool MIXED, bool IDX>
 __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem<CH>& sm, int lane) {
     const int i = it.inst;
     const int64_t ko = it.ko;
@@ -307,15 +307,15 @@ __device__ void run_wave_item(const BatchDevArgs& a, const WaveItem it, WaveSmem
     const int64_t k0 = ka + per * it.s + min((int64_t)it.s, rem);
     const int64_t k1 = k0 + per + ((int64_t)it.s < rem ? 1 : 0);
     if (k0 >= k1) return;
-    wave_eval_block<MIXED>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m, k0, k1, a.yq + qo,
-                           lane);
+    wave_eval_block<MIXED, false, kHoisted, false, IDX>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h,
+                                                        rh, m, k0, k1, a.yq + qo, lane, IDX ? a.idx + qo : nullptr);
 }
 
 // (at least 5 wavefronts per SIMD up to 3 rows per lane: the register
 // budget this asks for, 96, holds those instantiations without spills and
 // lets the 4096-curve batch's items all start in the first round; wider
 // spans are LDS-bound anyway)
-template <int CH, int WPG, bool BUILD, bool MIXED>
+template <int CH, int WPG, bool BUILD, bool MIXED, bool IDX>
 __global__ __launch_bounds__(WPG * kWave) __attribute__((amdgpu_waves_per_eu(CH <= 3 ? 5 : 1, 8))) void
 wave_items_kernel(BatchDevArgs a) {
     __shared__ WaveSmem<CH> smem[WPG];
@@ -323,7 +323,7 @@ wave_items_kernel(BatchDevArgs a) {
     const int wid = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * WPG;
     for (int64_t w = (int64_t)blockIdx.x * WPG + wid; w < a.n_witems; w += stride)
-        run_wave_item<CH, BUILD, MIXED>(a, a.witems[w], smem[wid], lane);
+        run_wave_item<CH, BUILD, MIXED, IDX>(a, a.witems[w], smem[wid], lane);
 }
 
 static int wave_ch_for(int64_t max_n) {
@@ -340,7 +340,8 @@ static int launch_waves(const BatchDevArgs& a, int grid_per_cu, int num_cu, hipS
     int64_t grid = groups;
     if (grid_per_cu > 0) grid = std::min<int64_t>(groups, (int64_t)num_cu * grid_per_cu);
     if (grid < 1) return SOLVE_OK;
-    wave_items_kernel<CH, WPG, BUILD, MIXED><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
+    if (a.idx) wave_items_kernel<CH, WPG, BUILD, MIXED, true><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
+    else wave_items_kernel<CH, WPG, BUILD, MIXED, false><<<(unsigned)grid, WPG * kWave, 0, s>>>(a);
     return SOLVE_OK;
 }
 
@@ -387,7 +388,7 @@ struct CoopItemSmem {
     int32_t bad;
 };
 
-template <int CH, bool BUILD, bool MIXED>
+template <int CH, bool BUILD, bool MIXED, bool IDX>
 __global__ __launch_bounds__(kCoopItemWaves * kWave) void coop_items_kernel(BatchDevArgs a) {
     __shared__ CoopItemSmem<CH> sm;
     const int tid = threadIdx.x;
@@ -476,8 +477,16 @@ __global__ __launch_bounds__(kCoopItemWaves * kWave) void coop_items_kernel(Batc
     const int64_t k0 = ka + per * p + min(p, rem);
     const int64_t k1 = k0 + per + (p < rem ? 1 : 0);
     if (k0 >= k1) return;
-    wave_eval_block<MIXED>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq[tid / kWave], lo, rs, j0, j1, x0, xl, h, rh, m, k0,
-                           k1, a.yq + qo, lane);
+    wave_eval_block<MIXED, false, kHoisted, false, IDX>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq[tid / kWave], lo, rs, j0,
+                                                        j1, x0, xl, h, rh, m, k0, k1, a.yq + qo, lane,
+                                                        IDX ? a.idx + qo : nullptr);
+}
+
+template <int CH, bool BUILD, bool MIXED>
+static void launch_coop_ch(const BatchDevArgs& a, unsigned g, hipStream_t s) {
+    constexpr int NT = kCoopItemWaves * kWave;
+    if (a.idx) coop_items_kernel<CH, BUILD, MIXED, true><<<g, NT, 0, s>>>(a);
+    else coop_items_kernel<CH, BUILD, MIXED, false><<<g, NT, 0, s>>>(a);
 }
 
 template <bool BUILD, bool MIXED>
@@ -485,13 +494,12 @@ static int launch_coop_any(int ch, const BatchDevArgs& a, hipStream_t s) {
     if (a.n_witems < 1) return SOLVE_OK;
     if (a.n_witems > 0x7fffffffLL) return SOLVE_E_SIZE;
     const unsigned g = (unsigned)a.n_witems;
-    constexpr int NT = kCoopItemWaves * kWave;
     switch (ch) {
-        case 1: coop_items_kernel<1, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
-        case 2: coop_items_kernel<2, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
-        case 3: coop_items_kernel<3, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
-        case 4: coop_items_kernel<4, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
-        case kWaveMaxCH: coop_items_kernel<kWaveMaxCH, BUILD, MIXED><<<g, NT, 0, s>>>(a); return SOLVE_OK;
+        case 1: launch_coop_ch<1, BUILD, MIXED>(a, g, s); return SOLVE_OK;
+        case 2: launch_coop_ch<2, BUILD, MIXED>(a, g, s); return SOLVE_OK;
+        case 3: launch_coop_ch<3, BUILD, MIXED>(a, g, s); return SOLVE_OK;
+        case 4: launch_coop_ch<4, BUILD, MIXED>(a, g, s); return SOLVE_OK;
+        case kWaveMaxCH: launch_coop_ch<kWaveMaxCH, BUILD, MIXED>(a, g, s); return SOLVE_OK;
         default: return SOLVE_E_ARG;
     }
 }
@@ -540,6 +548,7 @@ void Batch::make_tables() {
                       : (tuning_.fused == 2)           ? kLaneBuildMaxN
                                                        : 0;
     for (int64_t i = 0; i < count_; ++i) {
+        if (uniform_[i] == kCurveSkip) continue;
         if (n_[i] <= prebuilt_max_n_) {
             lane_.push_back((int32_t)i);
             lane_max_n_ = std::max(lane_max_n_, n_[i]);
@@ -555,6 +564,7 @@ void Batch::make_tables() {
     std::vector<double> cost;
     for (int64_t i = 0; i < count_; ++i) {
         const int64_t n = n_[i];
+        if (uniform_[i] == kCurveSkip) continue;
         const bool lane_built = n <= prebuilt_max_n_;
         if (lane_built && !uniform_[i]) continue;  // y'' only: phase 1 does it all
         const int bk = (n <= rows) ? (int)(n - 1) : lane_built ? rows - 1 : kWaveBlock;
@@ -622,8 +632,10 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
     for (int64_t i = 0; i < count; ++i) {
         n_[i] = koff[i + 1] - koff[i];
         m_[i] = qoff[i + 1] - qoff[i];
-        if (uniform) uniform_[i] = uniform[i] ? 1 : 0;
-        if (n_[i] < 3 || n_[i] > SOLVE_MAX_N_BATCH || m_[i] < (uniform_[i] ? 1 : 0)) return SOLVE_E_SIZE;
+        if (uniform) uniform_[i] = uniform[i] > kCurveSkip ? 1 : uniform[i];
+        if (n_[i] < 3 || m_[i] < 0) return SOLVE_E_SIZE;
+        if (uniform_[i] == kCurveSkip) continue;  // another kernel takes this curve
+        if (n_[i] > SOLVE_MAX_N_BATCH || m_[i] < (uniform_[i] ? 1 : 0)) return SOLVE_E_SIZE;
         max_n_ = std::max(max_n_, n_[i]);
     }
     count_ = count;
@@ -666,13 +678,13 @@ int Batch::upload(hipStream_t s) {
 }
 
 int Batch::launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
-                  const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s) {
-    return launch_with_tables(d_tables_, x, y, sd, ed, koff, qoff, yq, ypp, status, s);
+                  const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s, int32_t* idx) {
+    return launch_with_tables(d_tables_, x, y, sd, ed, koff, qoff, yq, ypp, status, s, idx);
 }
 
 int Batch::launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
                               const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
-                              int32_t* status, hipStream_t s) {
+                              int32_t* status, hipStream_t s, int32_t* idx) {
     if (!tables || !x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
     BatchDevArgs a;
     a.x = x;
@@ -684,6 +696,7 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     a.yq = yq;
     a.ypp = ypp;
     a.status = status;
+    a.idx = idx;
     a.witems = (const WaveItem*)tables;
     a.n_witems = (int64_t)witems_.size();
     a.lane_curves = (const int32_t*)((const char*)tables + offset_lane());
@@ -841,6 +854,14 @@ extern "C" int spline_plan_run(spline_plan* p, const double* x, const double* y,
     if (!p) return SOLVE_E_ARG;
     DeviceGuard g(p->batch.device());
     return p->batch.launch(x, y, sd, ed, koff, qoff, yq, ypp, status, (hipStream_t)stream);
+}
+
+extern "C" int spline_plan_run_indexed(spline_plan* p, const double* x, const double* y, const double* sd,
+                                       const double* ed, const int64_t* koff, const int64_t* qoff, double* yq,
+                                       double* ypp, int32_t* idx, int32_t* status, void* stream) {
+    if (!p || !idx) return SOLVE_E_ARG;
+    DeviceGuard g(p->batch.device());
+    return p->batch.launch(x, y, sd, ed, koff, qoff, yq, ypp, status, (hipStream_t)stream, idx);
 }
 
 extern "C" int spline_plan_capture(spline_plan* p, const double* x, const double* y, const double* sd,

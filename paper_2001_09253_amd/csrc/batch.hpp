@@ -24,6 +24,7 @@
 
 namespace spl {
 
+constexpr uint8_t kCurveSkip = 2;    // Batch::plan: a curve the batch's kernels leave alone
 constexpr int kLaneBuildMaxN = 256;  // curves up to this many knots are built in phase 1
 constexpr int kBatchHalo = 128;      // halo rows on either side of a knot block
 constexpr int kWaveMaxCH = 8;        // rows per lane of the largest wave span
@@ -59,6 +60,7 @@ struct BatchDevArgs {
     int64_t n_lane;
     int64_t prebuilt_max_n;      // curves up to this length were built in phase 1 (0: none)
     int32_t* bad;                // per curve, from phase 1: 1 if its knots are not increasing
+    int32_t* idx;                // nullable: the interval of every query (CSR like yq, per curve)
 };
 
 // Host side of a batch: the work tables and the device buffers that hold them.
@@ -71,7 +73,8 @@ public:
 
     // Plan from host offsets; returns a SOLVE_* code.  uniform (nullable):
     // per curve, 0 = no uniform queries (y'' only: its queries are evaluated
-    // by another kernel; m may then be 0).
+    // by another kernel; m may then be 0), kCurveSkip = the batch's kernels
+    // leave the curve alone (another launch solves it; any n >= 3).
     int plan(int64_t count, const int64_t* koff, const int64_t* qoff, const spline_tuning& t, uint32_t precision,
              const uint8_t* uniform = nullptr);
     // Copy the tables to the device (async on s); the host tables must stay
@@ -84,11 +87,13 @@ public:
     // Launch one run on device-resident data with the tables at the device
     // address tables (as written by write_tables), or with the plan's own
     // uploaded tables (launch).
+    // idx (nullable): the interval of every query, written by the same
+    // kernels compiled with the index store.
     int launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
-               const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s);
+               const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s, int32_t* idx = nullptr);
     int launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
                            const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
-                           int32_t* status, hipStream_t s);
+                           int32_t* status, hipStream_t s, int32_t* idx = nullptr);
 
     int64_t count() const { return count_; }
     const spline_tuning& tuning() const { return tuning_; }

@@ -137,7 +137,12 @@ struct Req {
     double t[4] = {0, 0, 0, 0};
     uint64_t bytes = 0;
     int passed_over = 0;
+    // recorded on the caller's stream at submit: the request's device outputs
+    // are written only after it (null when no output is device memory)
+    hipEvent_t ev = nullptr;
     bool explicit_q() const { return !xq.empty(); }
+    // too long for the batched kernels: solved by the single-curve kernels
+    bool solo() const { return n > SOLVE_MAX_N_BATCH; }
 };
 using ReqP = std::shared_ptr<Req>;
 
@@ -211,6 +216,9 @@ struct solve_ctx {
     // copy on the legacy stream would collide with a batch being captured)
     std::mutex in_mu;
     hipStream_t in_stream = nullptr;
+    // events recorded on the caller's stream (cfg.stream), reused
+    std::mutex ev_mu;
+    std::vector<hipEvent_t> ev_free;
     // plain mode
     std::mutex plain_mu;
     hipStream_t plain_stream = nullptr;
@@ -239,6 +247,27 @@ void finish_locked(solve_ctx* c, const ReqP& r, int status, int code) {
     if (status == SOLVE_DONE) ++c->n_completed; else ++c->n_failed;
 }
 
+hipEvent_t event_get(solve_ctx* c) {
+    {
+        std::lock_guard<std::mutex> g(c->ev_mu);
+        if (!c->ev_free.empty()) {
+            hipEvent_t e = c->ev_free.back();
+            c->ev_free.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void event_put(solve_ctx* c, hipEvent_t& e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(c->ev_mu);
+    c->ev_free.push_back(e);
+    e = nullptr;
+}
+
 // Stage, copy and launch one batch on slot s (called without the lock; the
 // slot is owned by the scheduler thread until its event completes).
 int launch_batch(solve_ctx* c, Slot& s) {
@@ -256,6 +285,7 @@ int launch_batch(solve_ctx* c, Slot& s) {
             xt += r.m;
             s.uniform[i] = 0;
         }
+        if (r.solo()) s.uniform[i] = spl::kCurveSkip;
         host_yq |= !r.yq_dev && !r.yq_pinned;
         host_ypp |= r.ypp_out && !r.ypp_dev && !r.ypp_pinned;
     }
@@ -305,6 +335,10 @@ int launch_batch(solve_ctx* c, Slot& s) {
     const bool use_graph = !(c->cfg.flags & SOLVE_NO_GRAPH);
     hipStream_t st = s.stream;
     s.drop_graph();
+    // device outputs are written only after the work the caller had queued
+    // on its stream when it submitted them
+    for (int64_t i = 0; i < count; ++i)
+        if (s.reqs[i]->ev && hipStreamWaitEvent(st, s.reqs[i]->ev, 0) != hipSuccess) return SOLVE_E_DEVICE;
     if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SOLVE_E_DEVICE;
     if (hipMemcpyAsync(s.din.p, s.hin.p, s.in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) rc = SOLVE_E_DEVICE;
     double* dx = s.din_at<double>(s.o_x);
@@ -315,6 +349,14 @@ int launch_batch(solve_ctx* c, Slot& s) {
         rc = s.batch->launch_with_tables(s.din_at<char>(s.o_tab), dx, dy, s.din_at<double>(s.o_sd),
                                          s.din_at<double>(s.o_ed), s.din_at<int64_t>(s.o_koff),
                                          s.din_at<int64_t>(s.o_qoff), dyq, dypp, s.dout_at<int32_t>(s.o_status), st);
+    // curves too long for the batched kernels: the single-curve kernels
+    // (y'' only, and one throw-away query, when the queries are explicit)
+    for (int64_t i = 0; i < count && !rc; ++i) {
+        const Req& r = *s.reqs[i];
+        if (!r.solo()) continue;
+        rc = spl::launch_solve_uniform(dx + s.koff[i], dy + s.koff[i], r.n, r.sd, r.ed, r.explicit_q() ? 1 : r.m,
+                                       dyq + s.qoff[i], dypp + s.koff[i], nullptr, nullptr, st);
+    }
     xo = 0;
     for (int64_t i = 0; i < count && !rc; ++i) {
         const Req& r = *s.reqs[i];
@@ -362,7 +404,9 @@ void deliver(Slot& s) {
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         Req& r = *s.reqs[i];
         if (s.failed) continue;
-        r.code = s.hout_at<int32_t>(s.o_status)[i];
+        // (the knots of every request were checked at submit; the batched
+        // kernels still report per curve, the single-curve path needs not)
+        r.code = r.solo() ? SOLVE_OK : s.hout_at<int32_t>(s.o_status)[i];
         if (!r.yq_dev && !r.yq_pinned) std::memcpy(r.yq_out, s.hout_at<double>(s.o_yq) + s.qoff[i], 8 * r.m);
         if (r.ypp_out && !r.ypp_dev && !r.ypp_pinned)
             std::memcpy(r.ypp_out, s.hout_at<double>(s.o_ypp) + s.koff[i], 8 * r.n);
@@ -417,6 +461,7 @@ void scheduler(solve_ctx* c) {
             if (!s.failed && hipStreamSynchronize(s.stream) != hipSuccess) s.failed = true;
             deliver(s);
             s.drop_graph();
+            for (auto& r : s.reqs) event_put(c, r->ev);
             lk.lock();
             for (auto& r : s.reqs) {
                 if (s.failed) finish_locked(c, r, SOLVE_ERROR, SOLVE_E_DEVICE);
@@ -433,7 +478,10 @@ void scheduler(solve_ctx* c) {
         }
         // 2. cancel queued work on shutdown
         if (c->stop && !c->queue.empty()) {
-            for (auto& r : c->queue) finish_locked(c, r, SOLVE_ERROR, SOLVE_E_STATE);
+            for (auto& r : c->queue) {
+                event_put(c, r->ev);
+                finish_locked(c, r, SOLVE_ERROR, SOLVE_E_STATE);
+            }
             c->queue.clear();
             c->cv_done.notify_all();
         }
@@ -475,6 +523,7 @@ void scheduler(solve_ctx* c) {
                     (void)hipStreamSynchronize(s.stream);
                     (void)hipGetLastError();
                     s.drop_graph();
+                    for (auto& r : s.reqs) event_put(c, r->ev);
                     lk.lock();
                     for (auto& r : s.reqs) finish_locked(c, r, SOLVE_ERROR, rc == SOLVE_E_ORDER ? rc : SOLVE_E_DEVICE);
                     c->resident -= s.bytes;
@@ -506,11 +555,15 @@ void scheduler(solve_ctx* c) {
     }
 }
 
-int copy_in(solve_ctx* c, std::vector<double>& dst, const double* src, int64_t n) {
+// Copy n doubles of a caller's input into dst; a device input is read after
+// `after` (recorded on the caller's stream), so after the work that produced it.
+int copy_in(solve_ctx* c, std::vector<double>& dst, const double* src, int64_t n, bool on_device, hipEvent_t after) {
     dst.resize((size_t)n);
-    if (is_device_ptr(src)) {
+    if (on_device) {
         std::lock_guard<std::mutex> g(c->in_mu);
-        hipError_t e = hipMemcpyAsync(dst.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost, c->in_stream);
+        hipError_t e = after ? hipStreamWaitEvent(c->in_stream, after, 0) : hipSuccess;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost, c->in_stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->in_stream);
         if (e != hipSuccess) return hip_fail("copy of a device input", e);
     } else {
@@ -531,21 +584,22 @@ int run_plain(solve_ctx* c, Req& r) {
     if (r.explicit_q()) rc = rc ? rc : c->pxq.ensure(8 * r.m);
     if (rc) return rc;
     r.t[1] = r.t[2] = now_s();
-    hipError_t e = hipMemcpyAsync(c->px.p, r.x.data(), 8 * r.n, hipMemcpyHostToDevice, s);
+    // device outputs: after the work the caller had queued when it submitted
+    hipError_t e = r.ev ? hipStreamWaitEvent(s, r.ev, 0) : hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(c->px.p, r.x.data(), 8 * r.n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->py.p, r.y.data(), 8 * r.n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->pstatus.p, 0, 4, s);  // SOLVE_OK; the kernels set E_ORDER only
     if (e != hipSuccess) return hip_fail("plain: input copy", e);
-    rc = spl::launch_build(c->px.as<double>(), c->py.as<double>(), r.n, r.sd, r.ed, c->pypp.as<double>(),
-                           c->pstatus.as<int32_t>(), s);
-    if (!rc) {
-        if (r.explicit_q()) {
-            e = hipMemcpyAsync(c->pxq.p, r.xq.data(), 8 * r.m, hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) return hip_fail("plain: query copy", e);
-            rc = spl::launch_eval_points(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
-                                         c->pxq.as<double>(), r.m, c->pyq.as<double>(), nullptr, nullptr, nullptr, s);
-        } else {
-            rc = spl::launch_eval_uniform_values(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
-                                                 r.m, c->pyq.as<double>(), s);
-        }
+    // the single-launch path of spline_solve_uniform (with explicit queries:
+    // its y'' and one throw-away uniform query, then the explicit evaluation)
+    rc = spl::launch_solve_uniform(c->px.as<double>(), c->py.as<double>(), r.n, r.sd, r.ed,
+                                   r.explicit_q() ? 1 : r.m, c->pyq.as<double>(), c->pypp.as<double>(),
+                                   c->pstatus.as<int32_t>(), nullptr, s);
+    if (!rc && r.explicit_q()) {
+        e = hipMemcpyAsync(c->pxq.p, r.xq.data(), 8 * r.m, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail("plain: query copy", e);
+        rc = spl::launch_eval_points(c->px.as<double>(), c->py.as<double>(), c->pypp.as<double>(), r.n,
+                                     c->pxq.as<double>(), r.m, c->pyq.as<double>(), nullptr, nullptr, nullptr, s);
     }
     if (rc) return rc;
     const hipMemcpyKind kq = r.yq_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -619,8 +673,7 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
                             solve_ticket* ticket_out) {
     if (!c || !knots || !values || !yq_out || !ticket_out) return SOLVE_E_ARG;
     const bool plain = (c->cfg.flags & SOLVE_PLAIN) != 0;
-    if (n < 3 || m < 1) return SOLVE_E_SIZE;
-    if (n > (plain ? SOLVE_MAX_N_BLOCK : SOLVE_MAX_N_BATCH)) return SOLVE_E_SIZE;
+    if (n < 3 || m < 1 || n > SOLVE_MAX_N_SOLVE) return SOLVE_E_SIZE;
     DevCtx g(c->cfg.device);
     ReqP r = std::make_shared<Req>();
     r->t[0] = now_s();
@@ -636,23 +689,49 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
     r->yq_pinned = kq == Mem::kPinned;
     r->ypp_dev = ypp_out && kp == Mem::kDevice;
     r->ypp_pinned = ypp_out && kp == Mem::kPinned;
-    int rc = copy_in(c, r->x, knots, n);
-    if (!rc) rc = copy_in(c, r->y, values, n);
-    if (!rc && xq) rc = copy_in(c, r->xq, xq, m);
-    if (rc) return rc;
-    for (int64_t j = 1; j < n; ++j)
-        if (!(r->x[j] > r->x[j - 1])) return SOLVE_E_ORDER;
+    const bool dx = is_device_ptr(knots), dy = is_device_ptr(values), dq = xq && is_device_ptr(xq);
+    // Device memory of the caller is ordered after the work queued on the
+    // caller's stream (cfg.stream, NULL = the legacy stream) when this call
+    // is made: inputs are read after it, outputs written after it.
+    hipEvent_t after = nullptr;
+    if (dx || dy || dq || r->yq_dev || r->ypp_dev) {
+        after = event_get(c);
+        if (!after) return SOLVE_E_DEVICE;
+        if (hipEventRecord(after, (hipStream_t)c->cfg.stream) != hipSuccess) {
+            event_put(c, after);
+            return hip_fail("solve_submit: event on the caller's stream", hipErrorUnknown);
+        }
+    }
+    int rc = copy_in(c, r->x, knots, n, dx, after);
+    if (!rc) rc = copy_in(c, r->y, values, n, dy, after);
+    if (!rc && xq) rc = copy_in(c, r->xq, xq, m, dq, after);
+    if (!rc)
+        for (int64_t j = 1; j < n; ++j)
+            if (!(r->x[j] > r->x[j - 1])) {
+                rc = SOLVE_E_ORDER;
+                break;
+            }
     r->bytes = footprint(n, m, xq != nullptr);
-    if (r->bytes > c->cfg.hbm_budget_bytes) return SOLVE_E_BUDGET;
+    if (!rc && r->bytes > c->cfg.hbm_budget_bytes) rc = SOLVE_E_BUDGET;
+    if (!rc && (r->yq_dev || r->ypp_dev)) r->ev = after;  // kept until the outputs are written
+    else event_put(c, after);
+    if (rc) {
+        event_put(c, r->ev);
+        return rc;
+    }
     if (plain) {
         {
             std::lock_guard<std::mutex> lk(c->mu);
-            if (c->stop) return SOLVE_E_STATE;
+            if (c->stop) {
+                event_put(c, r->ev);
+                return SOLVE_E_STATE;
+            }
             r->id = c->next_ticket++;
             ++c->n_submitted;
             c->tickets[r->id] = r;
         }
         const int prc = run_plain(c, *r);
+        event_put(c, r->ev);
         std::lock_guard<std::mutex> lk(c->mu);
         if (prc == SOLVE_OK) finish_locked(c, r, SOLVE_DONE, SOLVE_OK);
         else finish_locked(c, r, SOLVE_ERROR, prc);
@@ -661,7 +740,10 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
         return SOLVE_OK;
     }
     std::lock_guard<std::mutex> lk(c->mu);
-    if (c->stop) return SOLVE_E_STATE;
+    if (c->stop) {
+        event_put(c, r->ev);
+        return SOLVE_E_STATE;
+    }
     r->id = c->next_ticket++;
     ++c->n_submitted;
     c->tickets[r->id] = r;
@@ -750,6 +832,7 @@ extern "C" int solve_destroy(solve_ctx* c) {
         (void)hipStreamDestroy(s->stream);
     }
     for (DevBuf* d : {&c->px, &c->py, &c->pypp, &c->pyq, &c->pxq, &c->pstatus}) d->release();
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->plain_stream);
     (void)hipStreamDestroy(c->in_stream);
     delete c;

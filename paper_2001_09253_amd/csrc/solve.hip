@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -51,13 +52,14 @@ struct BlockSolve {
 
 // Sparse curves (few queries per interval): every query searches the block's
 // knots.
-template <int BK>
+template <int BK, bool IDX>
 __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double* __restrict__ x,
                                                                    const double* __restrict__ y, int64_t n,
                                                                    double sd, double ed, int64_t m,
                                                                    double* __restrict__ yq,
                                                                    double* __restrict__ ypp,
-                                                                   int32_t* __restrict__ status, int64_t nblocks) {
+                                                                   int32_t* __restrict__ status, int64_t nblocks,
+                                                                   int32_t* __restrict__ idx) {
     using B = BlockSolve<BK>;
     __shared__ double sx[B::kSpan + 2];
     __shared__ double sy[B::kSpan + 2];
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(kSolveBlock) void solve_blocks_kernel(const double*
                 const double q = uniform_query_at(x0, xl, h, m, kda, k, loc);
                 const int li = (int)lower_bound_idx(kx, 1, nb - 1, q) - 1;
                 yq[k] = newint_rec(q, rec[li]);
+                if constexpr (IDX) idx[k] = j0 + li;
             }
         }
         __syncthreads();  // the LDS is reused by the next block
@@ -155,11 +158,11 @@ struct WaveSolveSmem {
     int32_t bq[kMaxWaveBK + 1];
 };
 
-template <int VARIANT, bool WT>
+template <int VARIANT, bool WT, bool IDX>
 __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
     double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nblocks, int bk,
-    int shares) {
+    int shares, int32_t* __restrict__ idx) {
     __shared__ WaveSolveSmem smem[kWavesPerGroup];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
@@ -208,8 +211,8 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     if (k0 >= k1) return;
     // (few wavefronts per SIMD here: the next interval's constants are read
     // while the current one is evaluated)
-    wave_eval_block<false, true, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h, rh, m,
-                                              k0, k1, yq, lane);
+    wave_eval_block<false, true, VARIANT, WT, IDX>(sm.sx, sm.sy, sm.so, sm.inv, sm.bq, lo, rs, j0, j1, x0, xl, h,
+                                                   rh, m, k0, k1, yq, lane, idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,10 +268,11 @@ __device__ __forceinline__ double uniform_query_d(double x0, double xl, double h
     return q;
 }
 
-template <int CH, bool VEC>
+template <int CH, bool VEC, bool IDX>
 __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
-    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int64_t chunks) {
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int64_t nseg, int64_t chunks,
+    int32_t* __restrict__ idx) {
     constexpr int R = kWave * CH;  // rows per chunk
     // knots and values of the last two chunks: sx[b][i] is knot i of the
     // chunk (i = R: the next chunk's first), b the chunk's parity
@@ -517,6 +521,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
         const int64_t k0 = (sp == 0) ? 0 : (sp >= n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, xp[0]);
         double kd = (double)k0;
         double* out = yq + k0;
+        int32_t* iout = IDX ? idx + k0 : nullptr;
         double q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
@@ -538,6 +543,7 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
                 if (it == kStreamLaneQ || __ballot(act) == 0ull) break;
                 if (act) {
                     *out++ = newint_rec(q, r);
+                    if constexpr (IDX) *iout++ = sp + i;
                     kd += 1.0;
                     q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
                 }
@@ -562,10 +568,14 @@ __global__ __launch_bounds__(kWave * kStreamWaves) void solve_stream_kernel(
                     rb.ba2 = readlane_f64(r.ba2, L);
                     const int64_t kb0 = readlane_i64(k, L);
                     const int64_t ke = readlane_i64(kend, L);
-                    for (int64_t kk = kb0 + lane; kk < ke; kk += kWave)
+                    const int32_t tb = __builtin_amdgcn_readlane(sp, L) + i;  // lane L's interval
+                    for (int64_t kk = kb0 + lane; kk < ke; kk += kWave) {
                         yq[kk] = newint_rec(uniform_query(x0, xl, h, m, kk), rb);
+                        if constexpr (IDX) idx[kk] = tb;
+                    }
                 }
                 out = yq + kend;
+                if constexpr (IDX) iout = idx + kend;
                 kd = (double)kend;
                 q = uniform_query_d<!FULL>(x0, xl, h, md1, kd);
             }
@@ -662,10 +672,11 @@ struct CoopSmem {
     int rs, re;
 };
 
-template <int VARIANT, bool WT>
+template <int VARIANT, bool WT, bool IDX>
 __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const double* __restrict__ x, const double* __restrict__ y, int64_t n64, double sd, double ed, int64_t m,
-    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int bk, int shares) {
+    double* __restrict__ yq, double* __restrict__ ypp, int32_t* __restrict__ status, int bk, int shares,
+    int32_t* __restrict__ idx) {
     __shared__ CoopSmem sm;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -775,44 +786,61 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const int64_t k0 = sm.wk[wid][0];
     const int64_t k1 = sm.wk[wid][1];
     if (k0 >= k1) return;
-    eval_block_kq<false, VARIANT, WT>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0, k1,
-                                      sm.wt[wid][0], sm.wt[wid][1], yq, lane);
+    eval_block_kq<false, VARIANT, WT, IDX>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0,
+                                           k1, sm.wt[wid][0], sm.wt[wid][1], yq, lane, idx);
+}
+
+// Per-device values looked up once (compute units, resident workgroups of a
+// kernel); relaxed atomics, since two host threads may make their first call
+// on a device at the same time (both then store the same value).
+constexpr int kMaxDevices = 64;
+
+static int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    return dev;
 }
 
 static int cu_count() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cached[dev]) {
-        int v = 0;
+    static std::atomic<int> cached[kMaxDevices];
+    const int dev = current_device();
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (!v) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-        cached[dev] = v;
+        cached[dev].store(v, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return v;
 }
 
-template <int BK>
-static int resident_per_cu() {
-    static int cached = 0;
-    if (!cached) {
-        int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_blocks_kernel<BK>, kSolveBlock, 0) !=
-                hipSuccess || v <= 0)
-            v = 1;
-        cached = v;
+// Workgroups of `kernel` (of `threads` threads) one compute unit holds at once.
+template <typename K>
+static int resident_per_cu(std::atomic<int>* cache, K kernel, int threads) {
+    std::atomic<int>& c = cache[current_device()];
+    int v = c.load(std::memory_order_relaxed);
+    if (!v) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel, threads, 0) != hipSuccess || v <= 0) v = 1;
+        c.store(v, std::memory_order_relaxed);
     }
-    return cached;
+    return v;
+}
+
+template <int BK, bool IDX>
+static int launch_blocks_t(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
+                           double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
+    static std::atomic<int> occ[kMaxDevices];
+    const int64_t nblocks = (n - 1 + BK - 1) / BK;
+    const int64_t slots = (int64_t)cu_count() * resident_per_cu(occ, solve_blocks_kernel<BK, IDX>, kSolveBlock);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblocks, slots));
+    solve_blocks_kernel<BK, IDX><<<(unsigned)grid, kSolveBlock, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
+                                                                          nblocks, idx);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
 template <int BK>
 static int launch_blocks(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
-                         double* ypp, int32_t* status, hipStream_t s) {
-    const int64_t nblocks = (n - 1 + BK - 1) / BK;
-    const int64_t slots = (int64_t)cu_count() * resident_per_cu<BK>();
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblocks, slots));
-    solve_blocks_kernel<BK><<<(unsigned)grid, kSolveBlock, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status,
-                                                                            nblocks);
-    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+                         double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
+    if (idx) return launch_blocks_t<BK, true>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
+    return launch_blocks_t<BK, false>(x, y, n, sd, ed, m, yq, ypp, status, nullptr, s);
 }
 
 // Results written through (agent-scope stores) while they fit well inside
@@ -827,7 +855,7 @@ static bool write_through(int64_t m) { return m <= ((int64_t)1 << 24); }
 // halo rows would dominate.
 template <int VARIANT>
 static int launch_waves_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
-                              double* yq, double* ypp, int32_t* status, hipStream_t s) {
+                              double* yq, double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
     // about 2048 queries per block of bk intervals; denser blocks are cut
     // into shares of at most about 2700 queries (each share solves the
@@ -838,12 +866,21 @@ static int launch_waves_solve(const double* x, const double* y, int64_t n, doubl
     const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / 2730.0)));
     const int64_t groups = (nblocks * shares + kWavesPerGroup - 1) / kWavesPerGroup;
     if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
-    if (write_through(m))
-        solve_waves_kernel<VARIANT, true><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(
-            x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk, shares);
-    else
-        solve_waves_kernel<VARIANT, false><<<(unsigned)groups, kWave * kWavesPerGroup, 0, s>>>(
-            x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk, shares);
+    const dim3 g((unsigned)groups), b(kWave * kWavesPerGroup);
+    if (idx) {
+        if (write_through(m))
+            solve_waves_kernel<VARIANT, true, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk,
+                                                                    shares, idx);
+        else
+            solve_waves_kernel<VARIANT, false, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk,
+                                                                     shares, idx);
+    } else if (write_through(m)) {
+        solve_waves_kernel<VARIANT, true, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk,
+                                                                 shares, nullptr);
+    } else {
+        solve_waves_kernel<VARIANT, false, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nblocks, bk,
+                                                                  shares, nullptr);
+    }
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
@@ -855,20 +892,28 @@ constexpr double kCoopShareQ = 5460.0;
 
 template <int VARIANT>
 static int launch_coop_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
-                             double* yq, double* ypp, int32_t* status, hipStream_t s, double block_q = kCoopBlockQ,
-                             double share_q = kCoopShareQ) {
+                             double* yq, double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
-    const int bk = (int)std::min<double>(kMaxWaveBK, std::max(1.0, std::round(block_q / queries_per_knot)));
+    const int bk = (int)std::min<double>(kMaxWaveBK, std::max(1.0, std::round(kCoopBlockQ / queries_per_knot)));
     const int64_t nblocks = (n - 1 + bk - 1) / bk;
     const double per_block = queries_per_knot * bk;
-    const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / share_q)));
+    const int shares = (int)std::min<double>(1 << 20, std::max(1.0, std::ceil(per_block / kCoopShareQ)));
     if (nblocks * shares > 0x7fffffffLL) return SOLVE_E_SIZE;
-    if (write_through(m))
-        solve_coop_kernel<VARIANT, true><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(
-            x, y, n, sd, ed, m, yq, ypp, status, bk, shares);
-    else
-        solve_coop_kernel<VARIANT, false><<<(unsigned)(nblocks * shares), kCoopThreads, 0, s>>>(
-            x, y, n, sd, ed, m, yq, ypp, status, bk, shares);
+    const dim3 g((unsigned)(nblocks * shares)), b(kCoopThreads);
+    if (idx) {
+        if (write_through(m))
+            solve_coop_kernel<VARIANT, true, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk, shares,
+                                                                   idx);
+        else
+            solve_coop_kernel<VARIANT, false, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk, shares,
+                                                                    idx);
+    } else if (write_through(m)) {
+        solve_coop_kernel<VARIANT, true, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk, shares,
+                                                                nullptr);
+    } else {
+        solve_coop_kernel<VARIANT, false, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, bk, shares,
+                                                                 nullptr);
+    }
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
@@ -876,17 +921,9 @@ static int launch_coop_solve(const double* x, const double* y, int64_t n, double
 // use allows 4 per SIMD).
 template <int CH>
 static int64_t stream_resident_waves() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (!cached[dev]) {
-        int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_stream_kernel<CH, true>, kWave * kStreamWaves, 0) !=
-                hipSuccess || v <= 0)
-            v = 1;
-        cached[dev] = v;
-    }
-    return (int64_t)cached[dev] * kStreamWaves * cu_count();
+    static std::atomic<int> occ[kMaxDevices];
+    return (int64_t)resident_per_cu(occ, solve_stream_kernel<CH, true, false>, kWave * kStreamWaves) * kStreamWaves *
+           cu_count();
 }
 
 // Segments: every SIMD must get the same number of them, since a SIMD holding
@@ -912,10 +949,9 @@ static int64_t stream_segments(int64_t chunks) {
 
 template <int CH>
 static int launch_stream_solve(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m,
-                               double* yq, double* ypp, int32_t* status, hipStream_t s, int64_t nseg = 0) {
+                               double* yq, double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
     const int64_t chunks = (n + kWave * CH - 1) / (kWave * CH);
-    if (nseg <= 0) nseg = stream_segments<CH>(chunks);
-    nseg = std::max<int64_t>(1, std::min(nseg, chunks));
+    const int64_t nseg = std::max<int64_t>(1, std::min(stream_segments<CH>(chunks), chunks));
     const int64_t groups = (nseg + kStreamWaves - 1) / kStreamWaves;
     if (groups > 0x7fffffffLL) return SOLVE_E_SIZE;
     // (default write-back stores: each store instruction here writes 64
@@ -923,12 +959,20 @@ static int launch_stream_solve(const double* x, const double* y, int64_t n, doub
     // partial lines)
     // 16-byte loads where x and y allow them
     const bool vec = (CH % 2 == 0) && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
-    if (vec)
-        solve_stream_kernel<CH, true><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
-                                                                                          status, nseg, chunks);
-    else
-        solve_stream_kernel<CH, false><<<(unsigned)groups, kWave * kStreamWaves, 0, s>>>(x, y, n, sd, ed, m, yq, ypp,
-                                                                                           status, nseg, chunks);
+    const dim3 g((unsigned)groups), b(kWave * kStreamWaves);
+    if (idx) {
+        if (vec)
+            solve_stream_kernel<CH, true, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nseg, chunks, idx);
+        else
+            solve_stream_kernel<CH, false, true><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nseg, chunks,
+                                                                 idx);
+    } else if (vec) {
+        solve_stream_kernel<CH, true, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nseg, chunks,
+                                                             nullptr);
+    } else {
+        solve_stream_kernel<CH, false, false><<<g, b, 0, s>>>(x, y, n, sd, ed, m, yq, ypp, status, nseg, chunks,
+                                                              nullptr);
+    }
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
@@ -940,26 +984,26 @@ static int launch_stream_solve(const double* x, const double* y, int64_t n, doub
 // in flight per compute unit.
 template <int VARIANT>
 static int launch_dense(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
-                        double* ypp, int32_t* status, hipStream_t s) {
+                        double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
     const double queries_per_knot = (double)m / (double)(n - 1);
     const double bk = std::min<double>(kMaxWaveBK, std::max(2.0, std::round(2048.0 / queries_per_knot)));
     const double wave_items = std::ceil((double)(n - 1) / bk) * std::max(1.0, std::ceil(queries_per_knot * bk / 2730.0));
     if (wave_items <= 32.0 * cu_count() || queries_per_knot >= 1024.0)
-        return launch_coop_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, s);
-    return launch_waves_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, s);
+        return launch_coop_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
+    return launch_waves_solve<VARIANT>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
 }
 
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
-                         double* ypp, int32_t* status, hipStream_t s) {
+                         double* ypp, int32_t* status, int32_t* idx, hipStream_t s) {
     // (thresholds from timings on MI355X: the dense kernels already win at 16
     // queries per interval, the blocks kernel at 4; below 10 the streaming
     // kernel wins from about 160K knots at up to 4 queries per interval (by
     // 3-4x at 2^22-2^26 knots) and from 2^20 knots at up to 10)
     const double queries_per_knot = (double)m / (double)(n - 1);
-    if (queries_per_knot >= 10.0) return launch_dense<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, s);
+    if (queries_per_knot >= 10.0) return launch_dense<kHoisted>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
     if (n >= kStreamMinN && (queries_per_knot < 4.0 || n >= ((int64_t)1 << 20)))
-        return launch_stream_solve<kStreamCH>(x, y, n, sd, ed, m, yq, ypp, status, s);
-    return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, s);
+        return launch_stream_solve<kStreamCH>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
+    return launch_blocks<256>(x, y, n, sd, ed, m, yq, ypp, status, idx, s);
 }
 
 }  // namespace spl
@@ -971,7 +1015,15 @@ extern "C" int spline_solve_uniform(const double* x, const double* y, int64_t n,
                                     void* stream) {
     if (!x || !y || !yq) return SOLVE_E_ARG;
     if (n < 3 || n > SOLVE_MAX_N_SOLVE || m < 1) return SOLVE_E_SIZE;
-    return launch_solve_uniform(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, (hipStream_t)stream);
+    return launch_solve_uniform(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int spline_solve_uniform_indexed(const double* x, const double* y, int64_t n, double start_deriv,
+                                            double end_deriv, int64_t m, double* yq, double* ypp, int32_t* idx,
+                                            int32_t* status, void* stream) {
+    if (!x || !y || !yq || !idx) return SOLVE_E_ARG;
+    if (n < 3 || n > SOLVE_MAX_N_SOLVE || m < 1) return SOLVE_E_SIZE;
+    return launch_solve_uniform(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, idx, (hipStream_t)stream);
 }
 
 extern "C" int spline_solve_uniform_variant(const double* x, const double* y, int64_t n, double start_deriv,
@@ -982,17 +1034,17 @@ extern "C" int spline_solve_uniform_variant(const double* x, const double* y, in
     hipStream_t s = (hipStream_t)stream;
     switch (variant) {
         case SOLVE_NEWINT_HOISTED:
-            return launch_dense<kHoisted>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kHoisted>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         case SOLVE_NEWINT_ORIG:
-            return launch_dense<kOrig>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kOrig>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         case SOLVE_NEWINT_NOINV:
-            return launch_dense<kNoinv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kNoinv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         case SOLVE_SPLINT_DIV:
-            return launch_dense<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kSplintDiv>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         case SOLVE_SPLINT_MUL:
-            return launch_dense<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kSplintMul>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         case SOLVE_HORNER:
-            return launch_dense<kHorner>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, s);
+            return launch_dense<kHorner>(x, y, n, start_deriv, end_deriv, m, yq, ypp, status, nullptr, s);
         default:
             return SOLVE_E_ARG;
     }

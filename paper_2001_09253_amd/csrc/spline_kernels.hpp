@@ -92,19 +92,27 @@ __device__ __forceinline__ int64_t first_query_above(double x0, double xl, doubl
     return first_query_above_r(x0, xl, h, (m > 1) ? 1.0 / h : 0.0, m, v);
 }
 
-// The rewritten interpolant of "Fast Interpolation" (newint) on [a, b] with
-// values u, v and second derivatives up, vp; inv_ba = 1/(b - a) is supplied by
-// the caller (computed once per interval).
+// The rewritten interpolant of "Fast Interpolation" (the equation for y with
+// its cubic part V, the form the paper calls newint) on [a, b], with values
+// u, v and second derivatives up, vp at a and b.  In the paper's notation
+// ba = b - a, xa = q - a, bx = b - q:
+//     y = (xa v + bx u + V / 6) / ba,
+//     V = (xa^2 - ba^2) xa vp + (bx^2 - ba^2) bx up,
+// so the only division is by ba; newint_num is the numerator and the caller
+// supplies inv_ba = 1/ba (once per interval on the hot path).
+__device__ __forceinline__ double newint_num(double q, double a, double b, double u, double v, double up,
+                                             double vp) {
+    const double ba = b - a;
+    const double xa = q - a;
+    const double bx = b - q;
+    const double ba2 = ba * ba;
+    const double V = (xa * xa - ba2) * xa * vp + (bx * bx - ba2) * bx * up;
+    return (xa * v + bx * u) + (1.0 / 6.0) * V;
+}
+
 __device__ __forceinline__ double newint(double q, double a, double b, double u, double v, double up,
                                          double vp, double inv_ba) {
-    double ba = b - a;
-    double xa = q - a;
-    double bx = b - q;
-    double ba2 = ba * ba;
-    double lower = xa * v + bx * u;
-    double C = (xa * xa - ba2) * xa * vp;
-    double D = (bx * bx - ba2) * bx * up;
-    return (lower + (1.0 / 6.0) * (C + D)) * inv_ba;
+    return newint_num(q, a, b, u, v, up, vp) * inv_ba;
 }
 
 // First and second derivative of the same cubic (derivatives of newint's
@@ -207,19 +215,6 @@ __device__ __forceinline__ Fwd fwd_compose(const Fwd& B, const Fwd& A) {
     return fwd_normalize(o);
 }
 
-// One Thomas row (a, b, c, d) applied after A.
-__device__ __forceinline__ Fwd fwd_apply_row(const Fwd& A, double a, double b, double c, double d) {
-    Fwd o;
-    o.m00 = c * A.m10;
-    o.m01 = c * A.m11;
-    o.m10 = b * A.m10 - a * A.m00;
-    o.m11 = b * A.m11 - a * A.m01;
-    o.r0 = d * A.m10 - a * A.r0;
-    o.r1 = d * A.m11 - a * A.r1;
-    o.al = -a * A.al;
-    return fwd_normalize(o);
-}
-
 // One Thomas row applied after A, without renormalising (the caller scales
 // the row so that the entries stay within a factor 1.5 per row).
 __device__ __forceinline__ Fwd fwd_apply_row_raw(const Fwd& A, double a, double b, double c, double d) {
@@ -314,18 +309,6 @@ __device__ __forceinline__ Fwd wave_excl_prefix_fwd_dpp(Fwd v, Fwd* incl_out) {
     v = fwd_comp<NORM>(v, dpp_fwd<kDppRowBcast31, 0xc>(v));
     *incl_out = v;
     return dpp_fwd<kDppWaveShr1, 0xf>(v);
-}
-
-// Exclusive prefix (in lane order) of Fwd maps over one wavefront.
-__device__ __forceinline__ Fwd wave_excl_prefix_fwd(Fwd v, int lane, Fwd* incl_out) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        Fwd o = shfl_up_fwd(v, d);
-        if (lane >= d) v = fwd_compose(v, o);
-    }
-    *incl_out = v;
-    Fwd ex = shfl_up_fwd(v, 1);
-    return lane == 0 ? fwd_identity() : ex;
 }
 
 // Exclusive suffix (later lanes are inner) of Bwd maps over one wavefront.
@@ -446,29 +429,6 @@ __device__ __forceinline__ void adaptive_halo(const double* __restrict__ x, int 
     *rs_out = halo_start(x, j0, eps, hmax, lane);
     *re_out = halo_end(x, n, j1, eps, hmax, lane);
 }
-
-// Cross-workgroup signalling.  On a multi-XCD device an agent-scope acquire
-// or release maintains the XCD's L2 (write back / invalidate), so a poll loop
-// must not acquire on every iteration: it polls with relaxed atomic loads and
-// acquires once, and a producer publishes with one release fence per
-// workgroup (after a barrier that orders the other lanes' stores).
-template <int SLEEP>
-__device__ __forceinline__ bool wait_flag_at_least(int32_t* flag, int32_t target, int limit, int32_t* timeout) {
-    int spins = 0;
-    bool ok = true;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(SLEEP);
-        if (++spins > limit) {
-            if (timeout) __hip_atomic_store(timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-            break;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok;
-}
-
-__device__ __forceinline__ void release_fence_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -810,10 +770,8 @@ struct alignas(16) Interval {
 __device__ __forceinline__ double newint_rec(double q, const Interval& r) {
     const double xa = q - r.a;
     const double bx = r.b - q;
-    const double lower = xa * r.v + bx * r.u;
-    const double C = (xa * xa - r.ba2) * xa * r.vp;
-    const double D = (bx * bx - r.ba2) * bx * r.up;
-    return (lower + (1.0 / 6.0) * (C + D)) * r.inv;
+    const double V = (xa * xa - r.ba2) * xa * r.vp + (bx * bx - r.ba2) * bx * r.up;
+    return ((xa * r.v + bx * r.u) + (1.0 / 6.0) * V) * r.inv;
 }
 
 template <int BLOCK, int QPT, int WIN>
@@ -1067,20 +1025,10 @@ __device__ __forceinline__ double interp_variant(double q, double a, double b, d
                                                  double vp) {
     if constexpr (V == kHorner) {
         return horner(power_coeffs(a, b, u, v, up, vp, 1.0 / (b - a)), q - a);
-    } else if constexpr (V == kOrig || V == kNoinv) {
-        const double ba = b - a;
-        const double xa = q - a;
-        const double bx = b - q;
-        const double ba2 = ba * ba;
-        const double lower = xa * v + bx * u;
-        const double C = (xa * xa - ba2) * xa * vp;
-        const double D = (bx * bx - ba2) * bx * up;
-        if constexpr (V == kOrig) {
-            const double inv_ba = 1.0 / ba;
-            return (lower + (1.0 / 6.0) * (C + D)) * inv_ba;
-        } else {
-            return (lower + (1.0 / 6.0) * (C + D)) / ba;
-        }
+    } else if constexpr (V == kOrig) {
+        return newint_num(q, a, b, u, v, up, vp) * (1.0 / (b - a));  // the reciprocal formed per query
+    } else if constexpr (V == kNoinv) {
+        return newint_num(q, a, b, u, v, up, vp) / (b - a);  // a division per query
     } else {
         const double hh = b - a;
         const double A = (b - q) / hh;
@@ -1130,10 +1078,11 @@ __device__ __forceinline__ void put_out(double* p, double v) {
     else *p = v;
 }
 
-template <bool MIXED, bool PREFETCH = false, int VARIANT = kHoisted, bool WT = false>
+template <bool MIXED, bool PREFETCH = false, int VARIANT = kHoisted, bool WT = false, bool IDX = false>
 __device__ void wave_eval_block(const double* sx, const double* sy, const double* so, const double* sinv,
                                 int32_t* bq, int lo, int rs, int j0, int j1, double x0, double xl, double h,
-                                double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane) {
+                                double rh, int64_t m, int64_t k0, int64_t k1, double* __restrict__ out, int lane,
+                                int32_t* __restrict__ iout = nullptr) {
     const double dl = (double)lane;
     // intervals of the range's first and last query: j0 plus the interior
     // knots of the block below each
@@ -1201,8 +1150,10 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                 // below 2^53 in double), so x0 + kr*h, one multiply then one
                 // add, is the position uniform_query(.., k) bit for bit (query
                 // m-1 aside, which is x[n-1] itself and is patched below)
-                double kr = kl0 + (double)ks;
+        double kr = kl0 + (double)ks;
                 double* __restrict__ ob = o + ks;
+                int32_t* __restrict__ ib = IDX ? iout + k0 + lane + ks : nullptr;
+                const int32_t tc = t0 + c;  // this interval (a5)
                 int r = ks;
                 for (; r + 2 * kWave <= ke; r += 2 * kWave) {
                     double q0, q1;
@@ -1212,6 +1163,11 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         const double s1 = (kr + (double)kWave) * h;
                         q0 = x0 + s0;
                         q1 = x0 + s1;
+                    }
+                    if constexpr (IDX) {
+                        ib[0] = tc;
+                        ib[kWave] = tc;
+                        ib += 2 * kWave;
                     }
                     if constexpr (VARIANT == kHorner) {
                         put_out<WT>(ob, horner(cf, q0 - av));
@@ -1256,8 +1212,12 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
                         const double cc = cubic_term<MIXED>(xa, bx, ba2, up, vp);
                         val = (l + (1.0 / 6.0) * cc) * inv;
                     }
-                    if (r + lane < ke) put_out<WT>(ob, val);
+                    if (r + lane < ke) {
+                        put_out<WT>(ob, val);
+                        if constexpr (IDX) ib[0] = tc;
+                    }
                     ob += kWave;
+                    if constexpr (IDX) ib += kWave;
                     kr += (double)kWave;
                 }
             }
@@ -1284,6 +1244,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
             const int t = t1;
             put_out<WT>(out + (m - 1), interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo],
                                                            sy[t + 1 - lo], so[t - rs], so[t + 1 - rs], sinv[t - j0]));
+            if constexpr (IDX) iout[m - 1] = t;
         }
         return;
     }
@@ -1301,6 +1262,7 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
         if (live) {
             put_out<WT>(out + k, interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo], sy[tl + 1 - lo],
                                                      so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]));
+            if constexpr (IDX) iout[k] = tl;
         }
     }
 }
@@ -1333,11 +1295,12 @@ __device__ __forceinline__ void kq_span(const int64_t* kq, int j0, int j1, int64
 // registers.  Few: 64 consecutive queries at a time, each lane stepping from
 // the wavefront's current interval.  Query m-1 (x[n-1] itself) is patched at
 // the end.
-template <bool MIXED, int VARIANT = kHoisted, bool WT = false>
+template <bool MIXED, int VARIANT = kHoisted, bool WT = false, bool IDX = false>
 __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy, const double* so,
                                               const double* sinv, const int64_t* kq, int lo, int rs, int j0, int j1,
                                               double x0, double xl, double h, int64_t m, int64_t k0, int64_t k1,
-                                              int t0, int t1, double* __restrict__ out, int lane) {
+                                              int t0, int t1, double* __restrict__ out, int lane,
+                                              int32_t* __restrict__ iout = nullptr) {
     const int nt = t1 - t0 + 1;
     if (k1 - k0 >= 96 * (int64_t)nt && k1 - k0 < ((int64_t)1 << 30)) {
         const double kl0 = (double)k0 + (double)lane;
@@ -1360,6 +1323,7 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
             // (one multiply, then one add) is uniform_query(.., k) bit for bit
             double kr = kl0 + (double)ks;
             double* __restrict__ ob = o + ks;
+            int32_t* __restrict__ ib = IDX ? iout + k0 + lane + ks : nullptr;
             int r = ks;
             for (; r + 2 * kWave <= ke; r += 2 * kWave) {
                 double q0, q1;
@@ -1369,6 +1333,11 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
                     const double s1 = (kr + (double)kWave) * h;
                     q0 = x0 + s0;
                     q1 = x0 + s1;
+                }
+                if constexpr (IDX) {
+                    ib[0] = t;
+                    ib[kWave] = t;
+                    ib += 2 * kWave;
                 }
                 if constexpr (VARIANT == kHoisted) {
                     // a6: newint with the interval's 1/(b - a) and (b - a)^2
@@ -1406,8 +1375,12 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
                 } else {
                     val = interp_variant<VARIANT>(q, av, bv, u, v, up, vp);
                 }
-                if (r + lane < ke) put_out<WT>(ob, val);
+                if (r + lane < ke) {
+                    put_out<WT>(ob, val);
+                    if constexpr (IDX) ib[0] = t;
+                }
                 ob += kWave;
+                if constexpr (IDX) ib += kWave;
                 kr += (double)kWave;
             }
         }
@@ -1421,15 +1394,18 @@ __device__ __forceinline__ void eval_block_kq(const double* sx, const double* sy
             int tl = t;
             while (tl + 1 <= t1 && kq[tl + 1 - j0] <= kk) ++tl;
             t = __shfl(tl, kWave - 1);  // the last lane's interval (queries increase with k)
-            if (live)
+            if (live) {
                 put_out<WT>(out + k, interp_one<VARIANT>(q, sx[tl - lo], sx[tl + 1 - lo], sy[tl - lo],
                                                          sy[tl + 1 - lo], so[tl - rs], so[tl + 1 - rs], sinv[tl - j0]));
+                if constexpr (IDX) iout[k] = tl;
+            }
         }
     }
     if (k1 == m && m > 1 && lane == 0) {
         const int t = t1;  // query m-1 is x[n-1] itself, in the last interval
         put_out<WT>(out + (m - 1), interp_one<VARIANT>(xl, sx[t - lo], sx[t + 1 - lo], sy[t - lo], sy[t + 1 - lo],
                                                        so[t - rs], so[t + 1 - rs], sinv[t - j0]));
+        if constexpr (IDX) iout[m - 1] = t;
     }
 }
 

@@ -287,27 +287,6 @@ def test_solve_uniform_sparse_long_curves(kind):
         assert_close(host(yq), o_yq, "%s sparse yq" % kind)
 
 
-@pytest.mark.parametrize("n,m", [(13000, 1 << 27), (1 << 24, 1 << 24), (1 << 22, 47 << 22)])
-def test_solve_uniform_full_size_sampled(n, m):
-    # the single-curve roofline point (m = 2^27), a size-sweep point past the
-    # last-level cache (m = n = 2^24) and a dense long curve: every y'' and a
-    # sample of 4096 queries (the first, the last, and random ones) against
-    # the oracle
-    x, y = w.paper_curve(np.random.default_rng(n % 1000 + 7), n)
-    ks = np.unique(np.concatenate([[0, 1, m - 2, m - 1], np.random.default_rng(9).integers(0, m, 4092)]))
-    xd, yd = dev(x), dev(y)
-    ypp = torch.empty_like(xd)
-    yq = torch.empty(m, dtype=torch.float64, device="cuda")
-    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
-    api.spline_solve_uniform(xd, yd, 1e32, 1e32, m, yq, ypp, st)
-    o_vals, o_ypp = oracle.spline_uniform_sample(x, y, 1e32, 1e32, m, ks)
-    assert int(host(st)[0]) == api.OK
-    assert_close(host(ypp), o_ypp, "full-size ypp n=%d" % n)
-    g = yq[torch.as_tensor(ks, device="cuda")]
-    assert_close(host(g), o_vals, "full-size yq n=%d m=%d" % (n, m))
-    del yq
-
-
 def test_solve_uniform_sparse_bad_knots():
     x, y = w.paper_curve(np.random.default_rng(43), 100000)
     x[77777] = x[77776]

@@ -2,13 +2,15 @@
 results against the FP64 oracle, the same result alone and inside a mix,
 admission under a small HBM budget, error paths, and an open-loop Poisson
 replay through both the batched and the plain path."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from gpu_util import assert_close, host
-from paper_2001_09253_amd import api, serve, workloads as w
+from gpu_util import assert_close, dev, host
+from paper_2001_09253_amd import _native, api, serve, workloads as w
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +164,75 @@ def test_plain_path_takes_curves_past_the_batch_limit():
         assert_close(yq, o_yq, "plain yq")
 
 
+@pytest.mark.parametrize("flags", [0, api.NO_GRAPH, api.PLAIN])
+def test_long_curves_through_the_request_api(flags):
+    # curves past the batched kernels' limit (up to 2^20 knots here) take the
+    # single-curve kernels, alone (plain) or beside batched requests
+    sizes = [(1 << 20, 1 << 20), (13, 2048), ((1 << 20) + 5, 100000), (api.MAX_N_BATCH + 1, 3000), (200, 5000),
+             (300000, 7)]
+    reqs = make_reqs(21, sizes, explicit={2})
+    ctx = api.solve_create(flags=flags)
+    try:
+        sts, res = run_all(ctx, reqs)
+    finally:
+        api.solve_destroy(ctx)
+    for r, (req, st, (yq, ypp)) in enumerate(zip(reqs, sts, res)):
+        assert st == api.DONE, r
+        o_yq, o_ypp = expected(req)
+        assert_close(ypp, o_ypp, "long request %d ypp" % r)
+        assert_close(yq, o_yq, "long request %d yq" % r)
+
+
+def delay(t, reps=40):
+    """Queue about a few milliseconds of work on the current stream."""
+    for _ in range(reps):
+        t.mul_(1.0)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_device_io_ordered_after_the_callers_stream(plain, own_stream):
+    # The knots and values are produced, and the outputs cleared, by work
+    # queued on the caller's stream just before solve_submit, behind a few
+    # milliseconds of other work: the library reads the inputs after it (the
+    # zeros there before would be refused as unordered knots) and writes the
+    # results after the clearing fill.
+    reqs = make_reqs(22, [(513, 40000), (13, 2048), (3000, 5000)], explicit={2})
+    s = torch.cuda.Stream() if own_stream else torch.cuda.default_stream()
+    ballast = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+    srcs = [(dev(x), dev(y), dev(xq) if xq is not None else None) for x, y, _, _, xq, _ in reqs]
+    torch.cuda.synchronize()
+    ctx = api.solve_create(flags=api.PLAIN if plain else 0, stream=s if own_stream else None)
+    try:
+        outs, tickets = [], []
+        for (x, y, sd, ed, xq, m), (sx, sy, sq) in zip(reqs, srcs):
+            xd = torch.zeros_like(sx)
+            yd = torch.zeros_like(sy)
+            qd = torch.zeros_like(sq) if sq is not None else None
+            yq = torch.zeros(m, dtype=torch.float64, device="cuda")
+            ypp = torch.zeros_like(sx)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                delay(ballast)
+                xd.copy_(sx)
+                yd.copy_(sy)
+                if qd is not None:
+                    qd.copy_(sq)
+                yq.fill_(-7.0)
+                ypp.fill_(-7.0)
+                tickets.append(api.solve_submit(ctx, xd, yd, sd, ed, qd, m, yq, ypp))
+            outs.append((yq, ypp, xd, yd, qd))
+        for t in tickets:
+            assert api.solve_wait(ctx, t) == api.DONE
+            assert api.solve_poll(ctx, t) == api.DONE
+    finally:
+        api.solve_destroy(ctx)
+    for r, (req, (yq, ypp, *_)) in enumerate(zip(reqs, outs)):
+        o_yq, o_ypp = expected(req)
+        assert_close(host(ypp), o_ypp, "ordered ypp %d" % r)
+        assert_close(host(yq), o_yq, "ordered yq %d" % r)
+
+
 def test_admission_under_a_small_budget():
     sizes = [(int(n), int(m)) for n, m in zip(*w.log_uniform_sizes(np.random.default_rng(6), 120, 0.1, 10))]
     reqs = make_reqs(6, sizes)
@@ -213,10 +284,12 @@ def test_submit_errors():
         with pytest.raises(api.SolveError) as e:
             api.solve_submit(ctx, x, y, 1e32, 1e32, None, 0, out)
         assert e.value.code == api.E_SIZE
-        big = np.linspace(0, 1, api.MAX_N_BATCH + 1)
-        with pytest.raises(api.SolveError) as e:
-            api.solve_submit(ctx, big, big, 1e32, 1e32, None, 10, out)
-        assert e.value.code == api.E_SIZE
+        # past the largest curve (checked before any input is read)
+        t = C.c_uint64()
+        rc = _native.lib().solve_submit(ctx, C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data),
+                                        api.MAX_N_SOLVE + 1, 1e32, 1e32, None, 10, C.c_void_p(out.ctypes.data),
+                                        None, C.byref(t))
+        assert rc == api.E_SIZE
         huge = np.empty(1 << 18)
         with pytest.raises(api.SolveError) as e:
             api.solve_submit(ctx, x, y, 1e32, 1e32, None, 1 << 18, huge)

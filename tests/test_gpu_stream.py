@@ -4,7 +4,8 @@ and more below 10: one wavefront per segment of 256-row chunks, the forward
 state carried from chunk to chunk, a chunk's back substitution started from
 the next chunk's scan).  Every y'' and every query against the FP64 oracle at chunk and
 segment edges, on adversarial spacings and with intervals holding many
-queries; sampled at the sweep's largest size; unordered knots anywhere."""
+queries; unordered knots anywhere.  (The sweep's large sizes are compared in
+full, every query, in test_gpu_index.py.)"""
 import numpy as np
 import pytest
 import torch
@@ -97,26 +98,6 @@ def test_stream_unaligned_inputs():
     g_yq, g_ypp, _ = run(x[1:], y[1:], 0.5, -0.5, m)
     np.testing.assert_array_equal(g_yq, host(yq))
     np.testing.assert_array_equal(g_ypp, host(ypp))
-
-
-@pytest.mark.parametrize("n,m", [(1 << 26, 1 << 26), (1 << 28, 1 << 28)])
-def test_stream_full_size_sampled(n, m):
-    # the size sweep's large points (m = n): every y'' and a sample of the
-    # queries (the first, the last and random ones) against the oracle
-    x, y = w.paper_curve(np.random.default_rng(n % 1000 + 11), n)
-    ks = np.unique(np.concatenate([[0, 1, m - 2, m - 1], np.random.default_rng(10).integers(0, m, 4092)]))
-    xd, yd = dev(x), dev(y)
-    ypp = torch.empty_like(xd)
-    yq = torch.empty(m, dtype=torch.float64, device="cuda")
-    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
-    api.spline_solve_uniform(xd, yd, 1e32, 1e32, m, yq, ypp, st)
-    o_vals, o_ypp = oracle.spline_uniform_sample(x, y, 1e32, 1e32, m, ks)
-    assert int(host(st)[0]) == api.OK
-    del xd, yd
-    g = yq[torch.as_tensor(ks, device="cuda")]
-    assert_close(host(g), o_vals, "stream full-size yq n=%d" % n)
-    del yq
-    assert_close(host(ypp), o_ypp, "stream full-size ypp n=%d" % n)
 
 
 @pytest.mark.parametrize("pos", [1, 255, 256, 257, 70000, (1 << 18) - 2, (1 << 18) - 1])
