@@ -346,6 +346,37 @@ int spline_plan_get_tuning(const spline_plan *plan, spline_tuning *out);
 
 int spline_plan_destroy(spline_plan *plan);
 
+/* ============================================================================
+ * Batched form without device allocation.
+ * ========================================================================== */
+
+/* Largest work table spline_batch_run_noalloc holds: 48 bytes per work item
+ * (a curve takes one item per 8192 queries or so, more past 512 knots), plus
+ * 4 bytes per curve when a first launch builds the short curves. */
+#define SOLVE_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* For callers that cannot allocate device memory (a serving loop with a fixed
+ * footprint, a harness that forbids hipMalloc): spline_plan_create followed
+ * by spline_plan_run in one call that allocates no device memory.  The work
+ * tables are planned on the host from koff_host/qoff_host (count + 1 host
+ * int64 each, as for spline_plan_create, with precision and tuning as there;
+ * tuning NULL = the library default) and copied into a file-scope device
+ * buffer of SOLVE_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds until the process ends; x, y, sd, ed, koff, qoff, yq, ypp, status and
+ * stream as for spline_plan_run, on the current device.  The kernels are
+ * those of spline_plan_run, so the results are the same bit for bit.  The
+ * call returns once the table copy is done (it waits for the work queued
+ * before it on `stream`); the kernels then run asynchronously.  Every call on
+ * one GPU uses that GPU's one buffer: calls that overlap on a GPU (from
+ * several host threads, or on several streams) race and must be serialised by
+ * the caller.  Not for stream capture (the table copy is waited for).
+ * Errors: E_ARG, E_SIZE (sizes as spline_plan_create, or the tables beyond
+ * SOLVE_NOALLOC_SCRATCH_BYTES), E_DEVICE. */
+int spline_batch_run_noalloc(int64_t count, const int64_t *koff_host, const int64_t *qoff_host,
+                             uint32_t precision, const spline_tuning *tuning, const double *x, const double *y,
+                             const double *sd, const double *ed, const int64_t *koff, const int64_t *qoff,
+                             double *yq, double *ypp, int32_t *status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

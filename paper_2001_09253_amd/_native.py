@@ -62,6 +62,7 @@ SIGNATURES = {
                                                           C.POINTER(_d)]),
     "spline_plan_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
     "spline_plan_destroy": (C.c_int, [_vp]),
+    "spline_batch_run_noalloc": (C.c_int, [_i64, _vp, _vp, _u32, C.POINTER(Tuning)] + [_vp] * 10),
 }
 
 

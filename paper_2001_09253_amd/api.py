@@ -24,6 +24,7 @@ PLAIN, NO_GRAPH = 1, 2
 MAX_N_BLOCK = 16384
 MAX_N_BATCH = 2048
 MAX_N_SOLVE = 1 << 30
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 _NAMES = {OK: "OK", E_ARG: "E_ARG", E_SIZE: "E_SIZE", E_ORDER: "E_ORDER", E_BUDGET: "E_BUDGET",
           E_DEVICE: "E_DEVICE", E_TICKET: "E_TICKET", E_STATE: "E_STATE"}
@@ -245,6 +246,26 @@ def spline_plan_get_tuning(plan):
     t = Tuning()
     _check(_native.lib().spline_plan_get_tuning(plan.handle, C.byref(t)), "spline_plan_get_tuning")
     return t
+
+
+def spline_batch_run_noalloc(koff, qoff, bufs, precision=FP64, tuning=None, status=None, stream=None):
+    """spline_plan_create + spline_plan_run without device allocation (the
+    tables go to the library's fixed device buffer).  koff/qoff: host int64
+    offsets; bufs as for spline_plan_run (device tensors, including the same
+    offsets on the device)."""
+    koff = np.ascontiguousarray(koff, dtype=np.int64)
+    qoff = np.ascontiguousarray(qoff, dtype=np.int64)
+    count = len(koff) - 1
+    n_tot, m_tot = int(koff[-1]), int(qoff[-1])
+    args = [_dev(bufs["x"], name="x", numel=n_tot), _dev(bufs["y"], name="y", numel=n_tot),
+            _dev(bufs["sd"], name="sd", numel=count), _dev(bufs["ed"], name="ed", numel=count),
+            _dev(bufs["koff"], torch.int64, "koff", count + 1), _dev(bufs["qoff"], torch.int64, "qoff", count + 1),
+            _dev(bufs["yq"], name="yq", numel=m_tot), _dev(bufs["ypp"], name="ypp", numel=n_tot)]
+    _check(_native.lib().spline_batch_run_noalloc(count, koff.ctypes.data_as(C.c_void_p),
+                                                  qoff.ctypes.data_as(C.c_void_p), int(precision),
+                                                  C.byref(tuning) if tuning is not None else None, *args,
+                                                  _dev(status, torch.int32, "status", count, optional=True),
+                                                  _stream(stream)), "spline_batch_run_noalloc")
 
 
 # -- request API ------------------------------------------------------------------------------

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -520,8 +521,8 @@ bool valid_tuning(const spline_tuning& t) {
 }
 
 Batch::~Batch() {
-    (void)hipFree(d_tables_);
-    (void)hipFree(d_bad_);
+    if (d_tables_) (void)hipFree(d_tables_);
+    if (d_bad_) (void)hipFree(d_bad_);
 }
 
 int Batch::ensure(void** p, size_t* cap, size_t bytes) {
@@ -617,7 +618,7 @@ void Batch::make_tables() {
 }
 
 int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const spline_tuning& t,
-                uint32_t precision, const uint8_t* uniform) {
+                uint32_t precision, const uint8_t* uniform, bool host_only) {
     if (count < 1 || !koff || !qoff) return SOLVE_E_ARG;
     if (count > 0x7fffffffLL) return SOLVE_E_SIZE;
     if (!valid_tuning(t)) return SOLVE_E_ARG;
@@ -645,6 +646,13 @@ int Batch::plan(int64_t count, const int64_t* koff, const int64_t* qoff, const s
     if (!num_cu_) {
         if (hipDeviceGetAttribute(&num_cu_, hipDeviceAttributeMultiprocessorCount, device_) != hipSuccess)
             return SOLVE_E_DEVICE;
+    }
+    if (host_only) {  // the tables stay on the host (the caller places them)
+        if (!valid_tuning(t)) return SOLVE_E_ARG;
+        tuning_ = t;
+        wave_ch_ = wave_ch_for(max_n_);
+        make_tables();
+        return SOLVE_OK;
     }
     return retile(t);
 }
@@ -684,7 +692,7 @@ int Batch::launch(const double* x, const double* y, const double* sd, const doub
 
 int Batch::launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
                               const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
-                              int32_t* status, hipStream_t s, int32_t* idx) {
+                              int32_t* status, hipStream_t s, int32_t* idx, int32_t* bad) {
     if (!tables || !x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
     BatchDevArgs a;
     a.x = x;
@@ -702,7 +710,7 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     a.lane_curves = (const int32_t*)((const char*)tables + offset_lane());
     a.n_lane = (int64_t)lane_.size();
     a.prebuilt_max_n = prebuilt_max_n_;
-    a.bad = (int32_t*)d_bad_;
+    a.bad = bad ? bad : (int32_t*)d_bad_;
     const bool mixed = precision_ == SOLVE_FP32_REFINE;
     if (a.n_lane > 0) {
         if (!a.bad) return SOLVE_E_ARG;
@@ -994,4 +1002,74 @@ extern "C" int spline_plan_destroy(spline_plan* p) {
     (void)hipDeviceSynchronize();
     delete p;
     return SOLVE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The batched path for callers that cannot allocate device memory: the work
+// tables (and the phase-1 flags) live in `scratch`, a file-scope device array
+// that every GPU the library runs on holds until the process ends, instead of
+// the buffers of a plan.  In host code `scratch` names a host-side stand-in;
+// its device address on each GPU comes from hipGetSymbolAddress, once per
+// device, and only that address is handed to copies and kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SOLVE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxNoAllocDevices = 64;
+
+struct ScratchAddr {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+ScratchAddr g_scratch[kMaxNoAllocDevices];
+
+// Device address of `scratch` on the current device `dev`, looked up on the
+// first call there (with that device current).
+int scratch_address(int dev, void** out) {
+    ScratchAddr& a = g_scratch[dev];
+    std::call_once(a.once, [&a] {
+        void* p = nullptr;
+        a.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        a.ptr = (a.err == hipSuccess) ? p : nullptr;
+    });
+    if (a.err != hipSuccess || !a.ptr) return SOLVE_E_DEVICE;
+    *out = a.ptr;
+    return SOLVE_OK;
+}
+
+}  // namespace
+
+extern "C" int spline_batch_run_noalloc(int64_t count, const int64_t* koff_host, const int64_t* qoff_host,
+                                        uint32_t precision, const spline_tuning* tuning, const double* x,
+                                        const double* y, const double* sd, const double* ed, const int64_t* koff,
+                                        const int64_t* qoff, double* yq, double* ypp, int32_t* status,
+                                        void* stream) {
+    if (!koff_host || !qoff_host || !x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxNoAllocDevices) return SOLVE_E_DEVICE;
+    void* ptr = nullptr;
+    int rc = scratch_address(dev, &ptr);
+    if (rc) return rc;
+    Batch b(dev);
+    rc = b.plan(count, koff_host, qoff_host, tuning ? *tuning : default_tuning(), precision, nullptr, true);
+    if (rc) return rc;
+    const size_t tab = (b.table_bytes() + 255) & ~(size_t)255;
+    const size_t bad = b.needs_bad() ? sizeof(int32_t) * (size_t)count : 0;
+    if (tab + bad > (size_t)SOLVE_NOALLOC_SCRATCH_BYTES) return SOLVE_E_SIZE;
+    hipStream_t s = (hipStream_t)stream;
+    if (b.table_bytes() > 0) {
+        // the tables go from host memory into the scratch array; the copy
+        // is waited for so that the host copy may go when this call returns
+        std::vector<unsigned char> host(b.table_bytes());
+        b.write_tables(host.data());
+        if (hipMemcpyAsync(ptr, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            return SOLVE_E_DEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return SOLVE_E_DEVICE;
+    }
+    // (the phase-1 flags are written by the phase-1 build before any work
+    // item reads them: nothing in the scratch array has to start at zero)
+    return b.launch_with_tables(ptr, x, y, sd, ed, koff, qoff, yq, ypp, status, s, nullptr,
+                                bad ? (int32_t*)((unsigned char*)ptr + tab) : nullptr);
 }

@@ -75,8 +75,10 @@ public:
     // per curve, 0 = no uniform queries (y'' only: its queries are evaluated
     // by another kernel; m may then be 0), kCurveSkip = the batch's kernels
     // leave the curve alone (another launch solves it; any n >= 3).
+    // host_only: build the work tables on the host only (no device buffer
+    // is allocated; launch them with launch_with_tables and a `bad` buffer).
     int plan(int64_t count, const int64_t* koff, const int64_t* qoff, const spline_tuning& t, uint32_t precision,
-             const uint8_t* uniform = nullptr);
+             const uint8_t* uniform = nullptr, bool host_only = false);
     // Copy the tables to the device (async on s); the host tables must stay
     // alive until the copy completes (they are members, so until re-planning).
     int upload(hipStream_t s);
@@ -91,9 +93,13 @@ public:
     // kernels compiled with the index store.
     int launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
                const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s, int32_t* idx = nullptr);
+    // bad (nullable): per-curve flags of the phase-1 build (count int32),
+    // instead of the plan's own buffer.
     int launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
                            const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
-                           int32_t* status, hipStream_t s, int32_t* idx = nullptr);
+                           int32_t* status, hipStream_t s, int32_t* idx = nullptr, int32_t* bad = nullptr);
+    // Whether the launch needs the per-curve `bad` flags (a phase-1 build).
+    bool needs_bad() const { return !lane_.empty(); }
 
     int64_t count() const { return count_; }
     const spline_tuning& tuning() const { return tuning_; }
