@@ -321,7 +321,9 @@ __global__ __launch_bounds__(WPG * kWave) __attribute__((amdgpu_waves_per_eu(CH 
 wave_items_kernel(BatchDevArgs a) {
     __shared__ WaveSmem<CH> smem[WPG];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    // (uniform over the wavefront, so held in a scalar register: the work
+    // item is then read with scalar loads and its loops branch on scalars)
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t stride = (int64_t)gridDim.x * WPG;
     for (int64_t w = (int64_t)blockIdx.x * WPG + wid; w < a.n_witems; w += stride)
         run_wave_item<CH, BUILD, MIXED, IDX>(a, a.witems[w], smem[wid], lane);
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(kCoopItemWaves * kWave) void coop_items_kernel(Batc
     __shared__ CoopItemSmem<CH> sm;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int role = (tid / kWave + (int)blockIdx.x) & (kCoopItemWaves - 1);
+    const int role = __builtin_amdgcn_readfirstlane((tid / kWave + (int)blockIdx.x) & (kCoopItemWaves - 1));
     constexpr int NT = kCoopItemWaves * kWave;
     const WaveItem it = a.witems[blockIdx.x];
     const int i = it.inst;

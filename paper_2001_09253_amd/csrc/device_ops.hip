@@ -2,6 +2,8 @@
 // asynchronous on the caller's stream, no allocation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "spline_kernels.hpp"
 #include "spline_solve.h"
 #include "internal.hpp"
@@ -28,17 +30,121 @@ __global__ __launch_bounds__(BLOCK) void eval_uniform_kernel(const double* __res
     eval_uniform_tile<BLOCK, QPT, WIN, MODE, NT_STORE>(x, y, ypp, n, m, k0, out, sm, threadIdx.x);
 }
 
-template <int BLOCK, int QPT>
+// Explicit queries: persistent workgroups, each staging the fence table of
+// the knots in LDS once and then taking tiles of BLOCK * QPT consecutive
+// queries (coalesced loads and stores; the queries may be in any order).
+// The intervals of a tile's smallest and largest query come from the fence
+// table; when the knots between them fit the LDS window (queries that are
+// sorted, or clustered) the window's knots, values and y'' are staged and
+// every query searches the window, else every query searches the fence
+// table and then global memory.
+constexpr int kFenceMax = 2048;  // fences in LDS (16 KB)
+constexpr int kPointWin = 512;   // staged window, in knots
+
+template <int BLOCK>
+struct PointSmem {
+    double fence[kFenceMax];
+    double wx[kPointWin];
+    double wy[kPointWin];
+    double wp[kPointWin];
+    double red[2 * (BLOCK / kWave)];
+    int64_t win[2];
+    int32_t nan_any;
+};
+
+template <int BLOCK, int QPT, bool DERIVS, bool IDX>
 __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __restrict__ x,
                                                             const double* __restrict__ y,
                                                             const double* __restrict__ ypp, int64_t n,
                                                             const double* __restrict__ xq, int64_t m,
                                                             double* __restrict__ yq, double* __restrict__ d1,
-                                                            double* __restrict__ d2, int32_t* __restrict__ idx) {
-    __shared__ EvalSmem<BLOCK, QPT, BLOCK * QPT + 2> sm;
-    __shared__ double red[3 * (BLOCK / kWave)];
-    const int64_t k0 = (int64_t)blockIdx.x * (BLOCK * QPT);
-    eval_points_tile<BLOCK, QPT>(x, y, ypp, n, xq, m, k0, yq, d1, d2, idx, sm, red, threadIdx.x);
+                                                            double* __restrict__ d2, int32_t* __restrict__ idx,
+                                                            int64_t stride, int nf) {
+    __shared__ PointSmem<BLOCK> sm;
+    constexpr int NW = BLOCK / kWave;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    for (int f = tid; f < nf; f += BLOCK) sm.fence[f] = x[(int64_t)f * stride];
+    __syncthreads();
+    constexpr int64_t Q = (int64_t)BLOCK * QPT;
+    for (int64_t k0 = (int64_t)blockIdx.x * Q; k0 < m; k0 += (int64_t)gridDim.x * Q) {
+        double q[QPT];
+        double qmin = __builtin_inf(), qmax = -__builtin_inf();
+        bool nan = false;
+#pragma unroll
+        for (int r = 0; r < QPT; ++r) {  // all loads of the tile first
+            const int64_t k = k0 + (int64_t)r * BLOCK + tid;
+            q[r] = k < m ? xq[k] : x[0];
+        }
+#pragma unroll
+        for (int r = 0; r < QPT; ++r) {
+            nan |= (q[r] != q[r]);
+            qmin = fmin(qmin, q[r]);
+            qmax = fmax(qmax, q[r]);
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            qmin = fmin(qmin, __shfl_xor(qmin, d));
+            qmax = fmax(qmax, __shfl_xor(qmax, d));
+        }
+        const bool wave_nan = __ballot(nan) != 0ull;
+        if (tid == 0) sm.nan_any = 0;
+        __syncthreads();  // (the previous tile is done with the window)
+        if (lane == 0) {
+            sm.red[wid] = qmin;
+            sm.red[NW + wid] = qmax;
+            if (wave_nan) sm.nan_any = 1;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            // intervals of the tile's smallest and largest query
+            double v = sm.red[tid * NW];
+            for (int w = 1; w < NW; ++w) v = tid == 0 ? fmin(v, sm.red[w]) : fmax(v, sm.red[NW + w]);
+            sm.win[tid] = clip_interval(count_below_fenced(x, n, sm.fence, nf, stride, v), n);
+        }
+        __syncthreads();
+        const int64_t ilo = sm.win[0];
+        const int64_t ihi = max(sm.win[1], ilo);
+        // a NaN query has no place in the order: the tile searches everything
+        const bool staged = !sm.nan_any && ihi - ilo + 2 <= kPointWin;
+        if (staged) {
+            const int W = (int)(ihi - ilo) + 2;
+            for (int t = tid; t < W; t += BLOCK) {
+                sm.wx[t] = x[ilo + t];
+                sm.wy[t] = y[ilo + t];
+                sm.wp[t] = ypp[ilo + t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < QPT; ++r) {
+                const int64_t k = k0 + (int64_t)r * BLOCK + tid;
+                if (k < m) {
+                    // every query of the tile lies in intervals ilo .. ihi:
+                    // its interval is ilo plus the window's interior knots below it
+                    const int li = (int)lower_bound_idx(sm.wx, 1, W - 2, q[r]) - 1;
+                    const double a = sm.wx[li], b = sm.wx[li + 1];
+                    const double u = sm.wy[li], v = sm.wy[li + 1];
+                    const double up = sm.wp[li], vp = sm.wp[li + 1];
+                    const double inv = 1.0 / (b - a);
+                    yq[k] = newint(q[r], a, b, u, v, up, vp, inv);
+                    if constexpr (DERIVS) {
+                        double g1, g2;
+                        newint_derivs(q[r], a, b, u, v, up, vp, inv, &g1, &g2);
+                        if (d1) d1[k] = g1;
+                        if (d2) d2[k] = g2;
+                    }
+                    if constexpr (IDX) idx[k] = (int32_t)(ilo + li);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < QPT; ++r) {
+                const int64_t k = k0 + (int64_t)r * BLOCK + tid;
+                if (k < m) eval_point<DERIVS, IDX>(x, y, ypp, n, sm.fence, nf, stride, q[r], k, yq, d1, d2, idx);
+            }
+        }
+    }
 }
 
 // Workgroup shape of the single-instance build: the fewest rows per lane
@@ -56,7 +162,6 @@ int launch_build(const double* x, const double* y, int64_t n, double sd, double 
 }
 
 constexpr int kEvalBlock = 256;
-constexpr int kEvalQpt = 4;   // explicit queries
 constexpr int kEvalWin = 256; // staged window of the uniform tiles
 
 template <int QPT, int WIN, int MODE>
@@ -88,13 +193,30 @@ int launch_eval_uniform_values(const double* x, const double* y, const double* y
     return launch_eval_uniform<kModeValue>(x, y, ypp, n, m, yq, s);
 }
 
+template <bool DERIVS, bool IDX>
+static int launch_points_t(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
+                           int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s) {
+    constexpr int QPT = 8;
+    constexpr int64_t Q = (int64_t)kEvalBlock * QPT;
+    const int64_t stride = std::max<int64_t>(1, (n + kFenceMax - 1) / kFenceMax);
+    const int nf = (int)((n + stride - 1) / stride);
+    const int64_t tiles = (m + Q - 1) / Q;
+    // one round of resident workgroups (5 per compute unit: 29 KB of LDS each)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * 5));
+    eval_points_kernel<kEvalBlock, QPT, DERIVS, IDX><<<(unsigned)grid, kEvalBlock, 0, s>>>(x, y, ypp, n, xq, m, yq, d1,
+                                                                                           d2, idx, stride, nf);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
 int launch_eval_points(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
                        int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s) {
-    constexpr int Q = kEvalBlock * kEvalQpt;
-    const int64_t tiles = (m + Q - 1) / Q;
-    if (tiles > 0x7fffffffLL) return SOLVE_E_SIZE;
-    eval_points_kernel<kEvalBlock, kEvalQpt><<<(unsigned)tiles, kEvalBlock, 0, s>>>(x, y, ypp, n, xq, m, yq, d1, d2, idx);
-    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+    const bool derivs = d1 || d2;
+    if (derivs && idx) return launch_points_t<true, true>(x, y, ypp, n, xq, m, yq, d1, d2, idx, s);
+    if (derivs) return launch_points_t<true, false>(x, y, ypp, n, xq, m, yq, d1, d2, nullptr, s);
+    if (idx) return launch_points_t<false, true>(x, y, ypp, n, xq, m, yq, nullptr, nullptr, idx, s);
+    return launch_points_t<false, false>(x, y, ypp, n, xq, m, yq, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace spl

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup) void solve_waves_kernel(
     int shares, int32_t* __restrict__ idx) {
     __shared__ WaveSolveSmem smem[kWavesPerGroup];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // (held in a scalar register)
     WaveSolveSmem& sm = smem[wid];
     const int n = (int)n64;
     const int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wid;
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
     const int lane = tid & (kWave - 1);
     // each wavefront's role rotates with the workgroup, so that the solves of
     // the workgroups sharing a compute unit fall on different SIMDs
-    const int wid = (tid / kWave + (int)blockIdx.x) & (kCoopWaves - 1);
+    const int wid = __builtin_amdgcn_readfirstlane((tid / kWave + (int)blockIdx.x) & (kCoopWaves - 1));
     const int n = (int)n64;
     const int64_t blk = blockIdx.x / shares;
     const int sh = (int)(blockIdx.x - blk * shares);
@@ -782,12 +782,14 @@ __global__ __launch_bounds__(kCoopThreads) void solve_coop_kernel(
         const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
         for (int j = j0 + tid; j < jend; j += kCoopThreads) ypp[j] = sm.so[j - rs];
     }
-    // 3. this wavefront's part of the block's queries
-    const int64_t k0 = sm.wk[wid][0];
-    const int64_t k1 = sm.wk[wid][1];
+    // 3. this wavefront's part of the block's queries (uniform values, held
+    // in scalar registers so that the interval loop branches on scalars)
+    const int64_t k0 = readlane_i64(sm.wk[wid][0], 0);
+    const int64_t k1 = readlane_i64(sm.wk[wid][1], 0);
     if (k0 >= k1) return;
     eval_block_kq<false, VARIANT, WT, IDX>(sm.sx, sm.sy, sm.so, sm.inv, sm.kq, base, rs, j0, j1, x0, xl, h, m, k0,
-                                           k1, sm.wt[wid][0], sm.wt[wid][1], yq, lane, idx);
+                                           k1, __builtin_amdgcn_readfirstlane(sm.wt[wid][0]),
+                                           __builtin_amdgcn_readfirstlane(sm.wt[wid][1]), yq, lane, idx);
 }
 
 // Per-device values looked up once (compute units, resident workgroups of a

@@ -711,17 +711,6 @@ __device__ void build_group(const double* __restrict__ x, const double* __restri
 // ---------------------------------------------------------------------------
 enum EvalMode : int { kModeValue = 0, kModeIndex = 1, kModeNoop = 2 };
 
-template <int BLOCK, int QPT, int WIN>
-struct EvalSmem {
-    static constexpr int kQ = BLOCK * QPT;
-    static constexpr int kWin = WIN;  // knots of a window the LDS holds
-    double sx[WIN];
-    double sy[WIN];
-    double sp[WIN];
-    double sinv[WIN];
-    int64_t win[2];
-};
-
 // Interval indices of the first and last query of the tile, found by waves 0
 // and 1 with ballot searches over the whole knot array.
 __device__ __forceinline__ void tile_window(const double* __restrict__ x, int64_t n, double qa, double qb,
@@ -1096,8 +1085,10 @@ __device__ void wave_eval_block(const double* sx, const double* sy, const double
             ca += __popcll(__ballot(j < j1 && xj < qa));
             cb += __popcll(__ballot(j < j1 && xj < qb));
         }
-        t0 = j0 + ca;
-        t1 = j0 + cb;
+        // (uniform: held in scalar registers, so that the interval loop
+        // below branches on scalars)
+        t0 = __builtin_amdgcn_readfirstlane(j0 + ca);
+        t1 = __builtin_amdgcn_readfirstlane(j0 + cb);
     }
     const int nt = t1 - t0 + 1;
     wave_sync();
@@ -1418,100 +1409,42 @@ __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __
     eval_uniform_range<BLOCK, QPT, WIN, MODE, NT_STORE>(x, y, ypp, n, m, k0, k1, out, sm, tid);
 }
 
-// Explicit queries in any order: the tile's window spans the bracket of its
-// smallest and largest query.
-template <int BLOCK, int QPT>
-__device__ void eval_points_tile(const double* __restrict__ x, const double* __restrict__ y,
-                                 const double* __restrict__ ypp, int64_t n, const double* __restrict__ xq,
-                                 int64_t m, int64_t k0, double* __restrict__ yq, double* __restrict__ d1,
-                                 double* __restrict__ d2, int32_t* __restrict__ idx,
-                                 EvalSmem<BLOCK, QPT, BLOCK * QPT + 2>& sm, double* red, int tid) {
-    using S = EvalSmem<BLOCK, QPT, BLOCK * QPT + 2>;
-    constexpr int NW = BLOCK / kWave;
-    const int lane = tid & (kWave - 1);
-    const int wid = tid / kWave;
-    const int64_t klast = min(m, k0 + (int64_t)S::kQ) - 1;
-    double qmin = __builtin_inf(), qmax = -__builtin_inf();
-    bool has_nan = false;
-#pragma unroll
-    for (int r = 0; r < QPT; ++r) {
-        const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-        if (k <= klast) {
-            const double q = xq[k];
-            has_nan |= (q != q);
-            qmin = fmin(qmin, q);
-            qmax = fmax(qmax, q);
-        }
+// Explicit queries in any order (a5 by search, a6): the number of knots
+// below q is found in two steps.  A fence table in LDS holds every stride-th
+// knot, fence[f] = x[f * stride] for f < nf (nf = ceil(n / stride)); with c
+// the number of fences below q, every knot below index (c - 1) stride + 1 is
+// below q and none from c stride on is, so a search of the knots between
+// (at most stride - 1 of them, in global memory) completes the count.  The
+// interval is clip(count - 1, 0, n - 2), the definition itself; a NaN query
+// is below nothing and takes interval 0 (its value is NaN).
+__device__ __forceinline__ int64_t count_below_fenced(const double* __restrict__ x, int64_t n, const double* fence,
+                                                      int nf, int64_t stride, double q) {
+    const int64_t c = lower_bound_idx(fence, 0, nf, q);  // fences below q
+    if (c == 0) return 0;
+    const int64_t lo = (c - 1) * stride + 1;
+    const int64_t hi = min(c * stride, n);
+    return lower_bound_idx(x, lo, hi - lo, q);
+}
+
+template <bool DERIVS, bool IDX>
+__device__ __forceinline__ void eval_point(const double* __restrict__ x, const double* __restrict__ y,
+                                           const double* __restrict__ ypp, int64_t n, const double* fence, int nf,
+                                           int64_t stride, double q, int64_t k, double* __restrict__ yq,
+                                           double* __restrict__ d1, double* __restrict__ d2,
+                                           int32_t* __restrict__ idx) {
+    const int64_t i = clip_interval(count_below_fenced(x, n, fence, nf, stride, q), n);
+    const double a = x[i], b = x[i + 1];
+    const double u = y[i], v = y[i + 1];
+    const double up = ypp[i], vp = ypp[i + 1];
+    const double inv = 1.0 / (b - a);
+    yq[k] = newint(q, a, b, u, v, up, vp, inv);
+    if constexpr (DERIVS) {
+        double g1, g2;
+        newint_derivs(q, a, b, u, v, up, vp, inv, &g1, &g2);
+        if (d1) d1[k] = g1;
+        if (d2) d2[k] = g2;
     }
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) {
-        qmin = fmin(qmin, __shfl_xor(qmin, d));
-        qmax = fmax(qmax, __shfl_xor(qmax, d));
-    }
-    has_nan = __ballot(has_nan) != 0ull;
-    if (lane == 0) {
-        red[wid] = qmin;
-        red[NW + wid] = qmax;
-        red[2 * NW + wid] = has_nan ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    qmin = red[0];
-    qmax = red[NW];
-    double any_nan = red[2 * NW];
-    for (int w2 = 1; w2 < NW; ++w2) {
-        qmin = fmin(qmin, red[w2]);
-        qmax = fmax(qmax, red[NW + w2]);
-        any_nan = fmax(any_nan, red[2 * NW + w2]);
-    }
-    // A NaN query has no order: search the whole array for that tile.
-    if (any_nan > 0.0) {
-        qmin = -__builtin_inf();
-        qmax = __builtin_inf();
-    }
-    tile_window(x, n, qmin, qmax, sm.win, tid);
-    __syncthreads();
-    const int64_t ilo = sm.win[0];
-    const int64_t ihi = max(sm.win[1], ilo);
-    const int64_t span = ihi - ilo;
-    const bool staged = span + 2 <= S::kWin;
-    if (staged) {
-        const int W = (int)span + 2;
-        for (int t = tid; t < W; t += BLOCK) {
-            sm.sx[t] = x[ilo + t];
-            sm.sy[t] = y[ilo + t];
-            sm.sp[t] = ypp[ilo + t];
-        }
-        __syncthreads();
-        for (int t = tid; t < W - 1; t += BLOCK) sm.sinv[t] = 1.0 / (sm.sx[t + 1] - sm.sx[t]);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < QPT; ++r) {
-        const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-        if (k <= klast) {
-            const double q = xq[k];
-            double a, b, u, v, up, vp, inv;
-            int64_t i;
-            if (staged) {
-                const int li = (int)lower_bound_idx(sm.sx, 1, span, q) - 1;
-                i = ilo + li;
-                a = sm.sx[li]; b = sm.sx[li + 1]; u = sm.sy[li]; v = sm.sy[li + 1];
-                up = sm.sp[li]; vp = sm.sp[li + 1]; inv = sm.sinv[li];
-            } else {
-                i = lower_bound_idx(x, ilo + 1, span, q) - 1;
-                a = x[i]; b = x[i + 1]; u = y[i]; v = y[i + 1]; up = ypp[i]; vp = ypp[i + 1];
-                inv = 1.0 / (b - a);
-            }
-            yq[k] = newint(q, a, b, u, v, up, vp, inv);
-            if (d1 || d2) {
-                double g1, g2;
-                newint_derivs(q, a, b, u, v, up, vp, inv, &g1, &g2);
-                if (d1) d1[k] = g1;
-                if (d2) d2[k] = g2;
-            }
-            if (idx) idx[k] = (int32_t)i;
-        }
-    }
+    if constexpr (IDX) idx[k] = (int32_t)i;
 }
 
 }  // namespace spl
