@@ -341,6 +341,18 @@ int spline_plan_autotune(spline_plan *plan, const double *x, const double *y, co
                          double *ypp, int reps, const char *cache_path, spline_tuning *best,
                          double *best_ms);
 
+/* The plan's work tables, for inspection (tests walk every index the kernels
+ * form from them).  *n_items receives the number of 48-byte work items,
+ * *n_lane the number of curves a first launch builds, *wave_rows the rows of
+ * the widest span one wavefront holds (64 x rows per lane).  dst (nullable:
+ * then only the counts): host memory of dst_bytes >= the tables' size, which
+ * receives the work items (each: int64 first knot, first output, query
+ * count; int32 curve, knot count; int16 first and end interval; int32 share,
+ * shares, padding), then, from the next multiple of 256 bytes, the n_lane
+ * int32 curve indices.  Errors: E_ARG, E_SIZE (dst too small). */
+int spline_plan_get_tables(const spline_plan *plan, void *dst, uint64_t dst_bytes, int64_t *n_items,
+                           int64_t *n_lane, int64_t *wave_rows);
+
 /* The tuning a plan uses now. */
 int spline_plan_get_tuning(const spline_plan *plan, spline_tuning *out);
 

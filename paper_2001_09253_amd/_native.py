@@ -61,6 +61,7 @@ SIGNATURES = {
     "spline_plan_autotune": (C.c_int, [_vp] + [_vp] * 8 + [C.c_int, C.c_char_p, C.POINTER(Tuning),
                                                           C.POINTER(_d)]),
     "spline_plan_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "spline_plan_get_tables": (C.c_int, [_vp, _vp, _u64, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "spline_plan_destroy": (C.c_int, [_vp]),
     "spline_batch_run_noalloc": (C.c_int, [_i64, _vp, _vp, _u32, C.POINTER(Tuning)] + [_vp] * 10),
 }

@@ -242,6 +242,26 @@ def spline_plan_autotune(plan, bufs, reps=10, cache_path=None):
     return best, ms.value
 
 
+WAVE_ITEM_DTYPE = np.dtype([("ko", "<i8"), ("qo", "<i8"), ("m", "<i8"), ("inst", "<i4"), ("n", "<i4"),
+                            ("j0", "<i2"), ("j1", "<i2"), ("s", "<i4"), ("S", "<i4"), ("pad", "<i4")])
+
+
+def spline_plan_get_tables(plan):
+    """(work items as a structured array, curves of the first launch,
+    rows of the widest span a wavefront holds)."""
+    ni, nl, rows = C.c_int64(), C.c_int64(), C.c_int64()
+    L = _native.lib()
+    _check(L.spline_plan_get_tables(plan.handle, None, 0, C.byref(ni), C.byref(nl), C.byref(rows)),
+           "spline_plan_get_tables")
+    off = (ni.value * WAVE_ITEM_DTYPE.itemsize + 255) & ~255
+    buf = np.zeros(off + 4 * nl.value + 16, dtype=np.uint8)
+    _check(L.spline_plan_get_tables(plan.handle, C.c_void_p(buf.ctypes.data), buf.nbytes, C.byref(ni), C.byref(nl),
+                                    C.byref(rows)), "spline_plan_get_tables")
+    items = buf[:ni.value * WAVE_ITEM_DTYPE.itemsize].view(WAVE_ITEM_DTYPE).copy()
+    lane = buf[off:off + 4 * nl.value].view(np.int32).copy()
+    return items, lane, rows.value
+
+
 def spline_plan_get_tuning(plan):
     t = Tuning()
     _check(_native.lib().spline_plan_get_tuning(plan.handle, C.byref(t)), "spline_plan_get_tuning")

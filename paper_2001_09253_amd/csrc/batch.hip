@@ -915,6 +915,19 @@ extern "C" int spline_plan_replay(spline_plan* p, void* stream) {
     return hipGraphLaunch(p->exec, (hipStream_t)stream) == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 
+extern "C" int spline_plan_get_tables(const spline_plan* p, void* dst, uint64_t dst_bytes, int64_t* n_items,
+                                      int64_t* n_lane, int64_t* wave_rows) {
+    if (!p || !n_items || !n_lane || !wave_rows) return SOLVE_E_ARG;
+    const Batch& b = p->batch;
+    *n_items = b.n_witems();
+    *n_lane = b.n_lane();
+    *wave_rows = b.wave_rows();
+    if (!dst) return SOLVE_OK;
+    if (dst_bytes < b.table_bytes()) return SOLVE_E_SIZE;
+    b.write_tables(dst);
+    return SOLVE_OK;
+}
+
 extern "C" int spline_plan_get_tuning(const spline_plan* p, spline_tuning* out) {
     if (!p || !out) return SOLVE_E_ARG;
     *out = p->batch.tuning();

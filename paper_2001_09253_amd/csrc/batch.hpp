@@ -110,6 +110,7 @@ public:
     int64_t total_n() const { return total_n_; }
     int64_t total_m() const { return total_m_; }
     int64_t n_witems() const { return (int64_t)witems_.size(); }
+    int64_t n_lane() const { return (int64_t)lane_.size(); }
     int wave_rows() const { return wave_ch_ * 64; }
 
 private:
