@@ -271,7 +271,9 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
  * wavefronts never wait on one another.  With tuning.fused = 2 the curves of
  * up to 256 knots are solved by a first launch instead; with tuning.fused = 3
  * a work item is a workgroup of four wavefronts, one of which solves the span
- * while all four evaluate its queries.
+ * while all four evaluate its queries; with tuning.fused = 4 persistent
+ * workgroups pipeline the items, one wavefront solving the next item while
+ * the others evaluate the current one.
  * ========================================================================== */
 
 typedef struct spline_plan spline_plan;
@@ -287,7 +289,12 @@ typedef struct spline_plan spline_plan;
  * launch, one workgroup of four wavefronts per work item (block must be 256,
  * grid_per_cu is ignored; queries_per_tile is the largest share of one
  * workgroup), one wavefront solving the span into LDS and all four
- * evaluating a quarter of the share each. */
+ * evaluating a quarter of the share each; fused = 4: persistent workgroups of
+ * four wavefronts (block must be 256, grid_per_cu is ignored), one round of
+ * them, each taking every G-th work item: while one wavefront solves the next
+ * item's span into one of two LDS buffers, the other three evaluate the
+ * current item from the other buffer (FP64; mixed precision runs as
+ * fused = 1). */
 typedef struct {
     int32_t block;
     int32_t queries_per_tile;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -507,6 +508,202 @@ static int launch_coop_any(int ch, const BatchDevArgs& a, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined cooperative form (tuning.fused = 4): persistent workgroups of
+// four wavefronts, each taking every G-th work item of the table (G the
+// grid).  While one wavefront (the role rotates from item to item) solves
+// the next item's span into one of two LDS buffers, the other three
+// evaluate the current item's queries from the other buffer; one workgroup
+// barrier separates the stages.  The solve of an item (latency-bound, one
+// wavefront) thus runs beside the evaluation and result stores of the one
+// before it instead of ahead of it.  Every item solves its own span (curves
+// up to 512 knots whole, else a block with halos), as with fused = 1.
+// ---------------------------------------------------------------------------
+template <int CH>
+struct PipeBuf {
+    static constexpr int kRows = kWave * CH;
+    double sx[kRows + 2];
+    double sy[kRows + 2];
+    double so[kRows + 2];
+    double inv[kRows];
+    int64_t ka, kb;  // the block's queries [ka, kb)
+    int32_t rs, lo, bad;
+};
+
+template <int CH>
+struct PipeSmem {
+    PipeBuf<CH> buf[2];
+    int32_t bq[kCoopItemWaves][kWave * CH + 1];
+};
+
+// The solve stage of one item by one wavefront, into buffer b: a1-a4 over
+// the span, the item's y'' written out (share 0), its status, the intervals'
+// 1/(b - a) and the block's first and last query.
+template <int CH>
+__device__ void pipe_solve(const BatchDevArgs& a, const WaveItem& it, PipeBuf<CH>& b, int lane) {
+    const int i = it.inst;
+    const int64_t ko = it.ko;
+    const int n = it.n;
+    const int64_t m = it.m;
+    const double* __restrict__ x = a.x + ko;
+    const double* __restrict__ y = a.y + ko;
+    const int j0 = it.j0;
+    const int j1 = it.j1;
+    const bool reporter = j0 == 0 && it.s == 0;
+    const bool whole = j0 == 0 && j1 == n - 1;
+    const int rs = whole ? 0 : max(0, j0 - kBatchHalo);
+    const int re = whole ? n : min(n, j1 + 1 + kBatchHalo);
+    bool bad = build_any<CH>(x, y, n, rs, re, a.sd[i], a.ed[i], b.sx, b.sy, b.so, lane);
+    if (!whole) {
+        bool bb = false;
+        for (int j = 1 + lane; j < n; j += kWave) bb |= !(x[j] > x[j - 1]);
+        bad = bad || (__ballot(bb) != 0ull);
+    }
+    const int lo = max(rs - 1, 0);
+    if (lane == 0) {
+        b.rs = rs;
+        b.lo = lo;
+        b.bad = bad ? 1 : 0;
+    }
+    if (bad) {
+        if (reporter) {
+            const double nan = __builtin_nan("");
+            if (a.ypp)
+                for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = nan;
+            if (a.status && lane == 0) a.status[i] = kStatusOrder;
+        }
+        return;
+    }
+    if (reporter && a.status && lane == 0) a.status[i] = kStatusOk;
+    if (it.s == 0 && a.ypp) {
+        const int jend = j1 + (j1 == n - 1 ? 1 : 0);  // the last block also owns the last knot
+        for (int j = j0 + lane; j < jend; j += kWave) a.ypp[ko + j] = b.so[j - rs];
+    }
+    for (int t = j0 + lane; t < j1; t += kWave) b.inv[t - j0] = 1.0 / (b.sx[t + 1 - lo] - b.sx[t - lo]);
+    // a5: the block's queries are those in (x_j0, x_j1] (from k = 0 for the first block)
+    if (lane == 0) {
+        const double x0 = x[0];
+        const double xl = x[n - 1];
+        const double h = uniform_step(x0, xl, m);
+        const double rh = (m > 1) ? 1.0 / h : 0.0;
+        b.ka = (j0 == 0) ? 0 : first_query_above_r(x0, xl, h, rh, m, b.sx[j0 - lo]);
+        b.kb = (j1 == n - 1) ? m : first_query_above_r(x0, xl, h, rh, m, b.sx[j1 - lo]);
+    }
+}
+
+// The evaluation stage: part `part` of `parts` of the item's share of the
+// block's queries, from buffer b (filled by pipe_solve in the stage before).
+template <int CH, bool IDX>
+__device__ void pipe_eval(const BatchDevArgs& a, const WaveItem& it, const PipeBuf<CH>& b, int32_t* bq, int part,
+                          int parts, int lane) {
+    const int64_t qo = it.qo;
+    const int64_t m = it.m;
+    const int n = it.n;
+    if (it.S == 0) return;  // y'' only (its queries are evaluated by another kernel)
+    if (b.bad) {
+        // unordered knots: the curve's share-0 first block fills its results with NaN
+        if (it.j0 == 0 && it.s == 0) {
+            const double nan = __builtin_nan("");
+            for (int64_t k = (int64_t)part * kWave + lane; k < m; k += (int64_t)parts * kWave) a.yq[qo + k] = nan;
+        }
+        return;
+    }
+    const double* __restrict__ x = a.x + it.ko;
+    const double x0 = x[0];
+    const double xl = x[n - 1];
+    const double h = uniform_step(x0, xl, m);
+    const double rh = (m > 1) ? 1.0 / h : 0.0;
+    // share s of S of the block's queries (as every item form cuts them),
+    // then this wavefront's part of the share
+    const int64_t len = max(b.kb - b.ka, (int64_t)0);
+    const int64_t per = len / it.S;
+    const int64_t rem = len % it.S;
+    const int64_t s0 = b.ka + per * it.s + min((int64_t)it.s, rem);
+    const int64_t slen = per + ((int64_t)it.s < rem ? 1 : 0);
+    const int64_t pper = slen / parts;
+    const int64_t prem = slen % parts;
+    const int64_t k0 = s0 + pper * part + min((int64_t)part, prem);
+    const int64_t k1 = k0 + pper + ((int64_t)part < prem ? 1 : 0);
+    if (k0 >= k1) return;
+    wave_eval_block<false, false, kHoisted, false, IDX>(b.sx, b.sy, b.so, b.inv, bq, b.lo, b.rs, it.j0, it.j1, x0, xl,
+                                                        h, rh, m, k0, k1, a.yq + qo, lane, IDX ? a.idx + qo : nullptr);
+}
+
+template <int CH, bool IDX>
+__global__ __launch_bounds__(kCoopItemWaves * kWave) void pipe_items_kernel(BatchDevArgs a) {
+    __shared__ PipeSmem<CH> sm;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t G = gridDim.x;
+    const int64_t first = blockIdx.x;
+    if (first >= a.n_witems) return;  // (the whole workgroup)
+    const int64_t P = (a.n_witems - first + G - 1) / G;  // items of this workgroup
+    if (wid == 0) pipe_solve<CH>(a, a.witems[first], sm.buf[0], lane);
+    __syncthreads();
+    for (int64_t p = 0; p < P; ++p) {
+        const bool next = p + 1 < P;
+        const int solver = (int)((p + 1) & (kCoopItemWaves - 1));  // rotates over the SIMDs
+        if (next && wid == solver) {
+            pipe_solve<CH>(a, a.witems[first + (p + 1) * G], sm.buf[(p + 1) & 1], lane);
+        } else {
+            // evaluators: every wavefront but this stage's solver
+            const int parts = next ? kCoopItemWaves - 1 : kCoopItemWaves;
+            const int part = (next && wid > solver) ? wid - 1 : wid;
+            pipe_eval<CH, IDX>(a, a.witems[first + p * G], sm.buf[p & 1], sm.bq[wid], part, parts, lane);
+        }
+        __syncthreads();
+    }
+}
+
+// The persistent grid: one round of the workgroups the device holds at once
+// (looked up once per device; relaxed atomics, since two host threads may
+// plan at the same time and then both store the same value).
+template <int CH>
+static int pipe_grid(int num_cu) {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (!v) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, pipe_items_kernel<CH, false>, kCoopItemWaves * kWave,
+                                                         0) != hipSuccess ||
+            v <= 0)
+            v = 1;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v * std::max(1, num_cu);
+}
+
+static int pipe_grid_for(int ch, int num_cu) {
+    switch (ch) {
+        case 1: return pipe_grid<1>(num_cu);
+        case 2: return pipe_grid<2>(num_cu);
+        case 3: return pipe_grid<3>(num_cu);
+        case 4: return pipe_grid<4>(num_cu);
+        default: return pipe_grid<kWaveMaxCH>(num_cu);
+    }
+}
+
+template <int CH>
+static void launch_pipe_ch(const BatchDevArgs& a, unsigned g, hipStream_t s) {
+    constexpr int NT = kCoopItemWaves * kWave;
+    if (a.idx) pipe_items_kernel<CH, true><<<g, NT, 0, s>>>(a);
+    else pipe_items_kernel<CH, false><<<g, NT, 0, s>>>(a);
+}
+
+static int launch_pipe_any(int ch, const BatchDevArgs& a, int grid, hipStream_t s) {
+    if (a.n_witems < 1) return SOLVE_OK;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.n_witems, grid));
+    switch (ch) {
+        case 1: launch_pipe_ch<1>(a, g, s); return SOLVE_OK;
+        case 2: launch_pipe_ch<2>(a, g, s); return SOLVE_OK;
+        case 3: launch_pipe_ch<3>(a, g, s); return SOLVE_OK;
+        case 4: launch_pipe_ch<4>(a, g, s); return SOLVE_OK;
+        case kWaveMaxCH: launch_pipe_ch<kWaveMaxCH>(a, g, s); return SOLVE_OK;
+        default: return SOLVE_E_ARG;
+    }
+}
+
 spline_tuning default_tuning() {
     spline_tuning t;
     t.block = 256;
@@ -517,7 +714,7 @@ spline_tuning default_tuning() {
 }
 
 bool valid_tuning(const spline_tuning& t) {
-    return (t.fused == 1 || t.fused == 2 || (t.fused == 3 && t.block == 256)) &&
+    return (t.fused == 1 || t.fused == 2 || ((t.fused == 3 || t.fused == 4) && t.block == 256)) &&
            (t.block == 64 || t.block == 128 || t.block == 256) &&
            t.queries_per_tile >= 64 && t.queries_per_tile <= (1 << 24) && t.grid_per_cu >= 0 && t.grid_per_cu <= 64;
 }
@@ -608,9 +805,13 @@ void Batch::make_tables() {
     std::vector<size_t> order(witems_.size());
     std::iota(order.begin(), order.end(), (size_t)0);
     std::stable_sort(order.begin(), order.end(), [&](size_t p, size_t q) { return cost[p] > cost[q]; });
-    const size_t per_group = tuning_.fused == 3 ? 1 : (size_t)(tuning_.block / kWave);
-    const size_t groups = (size_t)std::max(1, num_cu_) *
-                          (tuning_.fused != 3 && tuning_.grid_per_cu > 0 ? (size_t)tuning_.grid_per_cu : 1);
+    // (the pipelined form: workgroup g takes items g, g + G, ... of the
+    // persistent grid G, so the stripes are G items wide)
+    const bool pipe = tuning_.fused == 4 && precision_ == SOLVE_FP64;
+    const size_t per_group = (tuning_.fused == 3 || pipe) ? 1 : (size_t)(tuning_.block / kWave);
+    const size_t groups = pipe ? (size_t)pipe_grid_for(wave_ch_, num_cu_)
+                               : (size_t)std::max(1, num_cu_) *
+                                     (tuning_.fused != 3 && tuning_.grid_per_cu > 0 ? (size_t)tuning_.grid_per_cu : 1);
     const size_t stripe = groups * per_group;
     for (size_t s0 = stripe; s0 < order.size(); s0 += 2 * stripe)
         std::reverse(order.begin() + s0, order.begin() + std::min(order.size(), s0 + stripe));
@@ -730,7 +931,9 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     // phase 2: the kernel holds the span solve only if some curve needs it
     const bool build = max_n_ > prebuilt_max_n_;
     int rc;
-    if (tuning_.fused == 3) {
+    if (tuning_.fused == 4 && !mixed && build) {
+        rc = launch_pipe_any(wave_ch_, a, pipe_grid_for(wave_ch_, num_cu_), s);
+    } else if (tuning_.fused == 3) {
         if (mixed) rc = launch_coop_any<false, true>(wave_ch_, a, s);
         else if (build) rc = launch_coop_any<true, false>(wave_ch_, a, s);
         else rc = launch_coop_any<false, false>(wave_ch_, a, s);
@@ -969,6 +1172,7 @@ extern "C" int spline_plan_autotune(spline_plan* p, const double* x, const doubl
             for (int cap : {2048, 4096, 8192})
                 for (int gpc : {0, 16}) cands.push_back(spline_tuning{block, cap, gpc, fused});
     for (int cap : {4096, 8192, 16384}) cands.push_back(spline_tuning{256, cap, 0, 3});
+    for (int cap : {4096, 8192, 16384}) cands.push_back(spline_tuning{256, cap, 0, 4});
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SOLVE_E_DEVICE;
     hipEvent_t e0, e1;

@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 # (block, queries_per_tile, grid_per_cu, fused)
 TUNINGS = [(64, 64, 0, 1), (64, 1024, 2, 1), (128, 2048, 0, 1), (256, 4096, 0, 1), (256, 16384, 3, 1),
            (64, 64, 0, 2), (128, 1024, 2, 2), (256, 4096, 0, 2), (256, 16384, 5, 2),
-           (256, 64, 0, 3), (256, 2048, 0, 3), (256, 16384, 0, 3)]
+           (256, 64, 0, 3), (256, 2048, 0, 3), (256, 16384, 0, 3),
+           (256, 64, 0, 4), (256, 2048, 0, 4), (256, 8192, 0, 4), (256, 16384, 0, 4)]
 # The two-launch form (a build kernel, then an evaluate kernel reading y''
 # back) faulted the GPU in its build kernel with a memory aperture violation
 # and no cause was found by reading it; it was taken out of the library, and
@@ -84,7 +85,7 @@ def test_batch_mixed_sizes_up_to_limit():
 
 
 @pytest.mark.parametrize("cap", [64, 1024, 1 << 20])
-@pytest.mark.parametrize("fused", [1, 2, 3])
+@pytest.mark.parametrize("fused", [1, 2, 3, 4])
 def test_batch_halo_blocks_worst_decay(cap, fused):
     # curves past one wavefront's rows are cut into knot blocks with halos;
     # alternating widths 1 and 1e-3 give the slowest decay of the dropped
@@ -100,7 +101,7 @@ def test_batch_halo_blocks_worst_decay(cap, fused):
     qoff = np.concatenate([[0], np.cumsum([m for _, m in sizes])]).astype(np.int64)
     b = w.Batch(koff, qoff, np.concatenate(xs), np.concatenate(ys), np.array([1e32, 0.0, -1.0, 1e32]),
                 np.array([1e32, 0.0, 1.0, 2.0]))
-    plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(256 if fused == 3 else 128, cap, 0, fused))
+    plan = api.spline_plan_create(b.koff, b.qoff, tuning=api.Tuning(256 if fused >= 3 else 128, cap, 0, fused))
     bufs, st = to_dev(b)
     api.spline_plan_run(plan, bufs, st)
     assert np.all(host(st) == 0)
@@ -115,7 +116,7 @@ def test_batch_single_instance_equals_plain_sizes():
     check_batch(b, host(bufs["yq"]), host(bufs["ypp"]), what="single")
 
 
-@pytest.mark.parametrize("fused", [1, 2, 3])
+@pytest.mark.parametrize("fused", [1, 2, 3, 4])
 def test_batch_invalid_instance_flags_status(fused):
     b = w.batch(seed=4, count=40)
     x = b.x.copy()
@@ -144,7 +145,7 @@ def test_plan_rejects_bad_sizes():
         api.spline_plan_create([0, 5], [0, 0])
     assert e.value.code == api.E_SIZE
     for bad in ((96, 1024, 0, 1), (512, 1024, 0, 1), (128, 1024, 0, 0), (256, 32, 0, 1), (256, 1024, -1, 1),
-                (256, 1024, 0, 4), (64, 1024, 0, 3)):
+                (256, 1024, 0, 5), (64, 1024, 0, 3), (128, 1024, 0, 4)):
         with pytest.raises(api.SolveError) as e:
             api.spline_plan_create([0, 5], [0, 10], tuning=api.Tuning(*bad))
         assert e.value.code == api.E_ARG

@@ -120,7 +120,7 @@ BATCH_SIZES = ([(3, 1), (3, 2), (4, 7), (13, 2048), (64, 64), (65, 30000), (128,
                 (2047, 2), (700, 90)] +
                [(int(n), int(m)) for n, m in zip(*w.log_uniform_sizes(np.random.default_rng(2), 200, 0.1, 10))])
 
-TUNINGS = [None, (256, 8192, 0, 1), (64, 2048, 16, 1), (256, 4096, 0, 2), (256, 8192, 0, 3)]
+TUNINGS = [None, (256, 8192, 0, 1), (64, 2048, 16, 1), (256, 4096, 0, 2), (256, 8192, 0, 3), (256, 8192, 0, 4)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS)

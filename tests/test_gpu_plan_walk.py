@@ -94,7 +94,8 @@ def walk(koff, qoff, precision, tuning):
 
 
 CONFIGS = [(api.FP64, None), (api.FP64, (256, 8192, 0, 1)), (api.FP64, (64, 2048, 16, 1)),
-           (api.FP64, (256, 4096, 0, 2)), (api.FP64, (256, 16384, 0, 3)), (api.FP32_REFINE, None)]
+           (api.FP64, (256, 4096, 0, 2)), (api.FP64, (256, 16384, 0, 3)), (api.FP64, (256, 8192, 0, 4)),
+           (api.FP32_REFINE, None)]
 
 
 @pytest.mark.parametrize("precision,tuning", CONFIGS)

@@ -62,7 +62,8 @@ def test_noalloc_equals_plan_run_twice():
 
 
 @pytest.mark.parametrize("precision,tuning", [(api.FP64, (256, 4096, 0, 2)), (api.FP64, (256, 8192, 0, 3)),
-                                              (api.FP64, (64, 2048, 16, 1)), (api.FP32_REFINE, None)])
+                                              (api.FP64, (256, 8192, 0, 4)), (api.FP64, (64, 2048, 16, 1)),
+                                              (api.FP32_REFINE, None)])
 def test_noalloc_tunings(precision, tuning):
     b = w.batch(seed=2, count=1500)
     run_both(b, precision, tuning)
