@@ -3,7 +3,9 @@
     python -m paper_2001_09253_amd.profiling stats <rocprofv3 dir> <out.txt> <command...>
         writes the per-kernel duration table of a --kernel-trace --stats run
         (average, and the median dispatch from the trace), headed by the
-        command that produced it and $PROFILE_NOTE, if set;
+        command that produced it and $PROFILE_NOTE, if set; with
+        $PROFILE_LAST = K also each kernel's last K dispatches (a bench
+        run's timed launches);
     python -m paper_2001_09253_amd.profiling traffic <kernel> <workload> <fetch dir> <write dir>
         <copy fetch dir> <copy write dir> <copy bytes> [<kernel substring>]
         scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over the
@@ -58,26 +60,42 @@ def _kernel_rows(prof_dir):
             for r in con.execute(q)]
 
 
-def _medians(prof_dir):
-    """Median dispatch duration (ns) per kernel from the run's kernel trace,
-    if the trace is there."""
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+
+
+def _durations(prof_dir):
+    """Dispatch durations (ns) per kernel in dispatch order, from the run's
+    kernel trace (empty without one)."""
     hits = glob.glob(os.path.join(prof_dir, "**", "*kernel_trace.csv"), recursive=True)
     if not hits:
         return {}
-    per = {}
+    rows = []
     with open(hits[0]) as f:
         for r in csv.DictReader(f):
-            per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    out = {}
-    for k, v in per.items():
-        v.sort()
-        out[k] = v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
-    return out
+            rows.append((int(r["Start_Timestamp"]), r["Kernel_Name"],
+                         int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    per = {}
+    for _, name, d in rows:
+        per.setdefault(name, []).append(d)
+    return per
 
 
-def stats(prof_dir, out_path, command, note=None):
+def _medians(prof_dir):
+    """Median dispatch duration (ns) per kernel from the run's kernel trace,
+    if the trace is there."""
+    return {k: _median(v) for k, v in _durations(prof_dir).items()}
+
+
+def stats(prof_dir, out_path, command, note=None, last=0):
+    """The summary; with last > 0 also the average and median of each
+    kernel's last `last` dispatches (the timed launches of a bench run, which
+    come after its warm-up and context launches)."""
     rows = _kernel_rows(prof_dir)
     med = _medians(prof_dir)
+    durs = _durations(prof_dir) if last > 0 else {}
     lines = ["# rocprofv3 --kernel-trace --stats", "# command: " + command,
              "# kernel sources: " + kernel_source_hash()]
     if note:
@@ -89,6 +107,15 @@ def stats(prof_dir, out_path, command, note=None):
         lines.append("%-72s %7s %12.3f %12s %12.3f %12.3f" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
                                                            "%.3f" % (m / 1e3) if m is not None else "-",
                                                            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    if last > 0 and durs:
+        lines += ["", "last %d dispatches of each kernel (the timed launches):" % last,
+                  "%-72s %7s %12s %12s" % ("kernel", "calls", "avg_us", "median_us")]
+        for r in rows:
+            v = durs.get(r["Name"], [])[-last:]
+            if not v:
+                continue
+            name = r["Name"] if len(r["Name"]) <= 72 else r["Name"][:69] + "..."
+            lines.append("%-72s %7d %12.3f %12.3f" % (name, len(v), sum(v) / len(v) / 1e3, _median(v) / 1e3))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -134,7 +161,8 @@ def traffic(kernel, workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy
 
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), os.environ.get("PROFILE_NOTE"))
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), os.environ.get("PROFILE_NOTE"),
+              int(os.environ.get("PROFILE_LAST", "0")))
     elif len(sys.argv) >= 9 and sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     else:
