@@ -629,7 +629,9 @@ def served_context(seconds, rate=2000.0):
                         "(13, 2048), host result buffers, 200 GB budget" % (rate, seconds),
             "served_p50_ms": sb["p50_ms"], "served_p99_ms": sb["p99_ms"], "plain_p50_ms": sp["p50_ms"],
             "plain_p99_ms": sp["p99_ms"], "served_steps_per_s": sb["steps_per_s"],
-            "plain_steps_per_s": sp["steps_per_s"], "requests": res_b.requests}
+            "plain_steps_per_s": sp["steps_per_s"], "requests": res_b.requests,
+            "served_peak_device_bytes": res_b.stats.get("peak_device_bytes"),
+            "served_peak_resident_bytes": res_b.stats.get("peak_resident_bytes")}
 
 
 def bench_sweep(args):

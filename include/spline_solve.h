@@ -81,7 +81,7 @@ typedef uint64_t solve_ticket;
 
 typedef struct {
     int device;                /* HIP device ordinal                                */
-    uint64_t hbm_budget_bytes; /* admission budget for resident request state       */
+    uint64_t hbm_budget_bytes; /* budget for the device buffers of resident requests */
     uint32_t max_slots;        /* max requests resident on the device at once       */
     uint32_t precision;        /* SOLVE_FP64 or SOLVE_FP32_REFINE                    */
     uint32_t flags;            /* SOLVE_PLAIN, SOLVE_NO_GRAPH                        */
@@ -102,8 +102,14 @@ typedef struct {
  * released with solve_destroy.  A background scheduler thread admits
  * requests against hbm_budget_bytes / max_slots and launches them in fused
  * batches (continuous batching) unless SOLVE_PLAIN is set, in which case
- * solve_submit runs the request synchronously.  Errors: E_ARG (null or bad
- * config), E_DEVICE. */
+ * solve_submit runs the request synchronously.  Admission keeps the summed
+ * footprints of the requests on the device (plus 4096 bytes per batch) within
+ * hbm_budget_bytes; each in-flight batch's device buffers are sized within
+ * what the budget leaves beside the other slots' buffers (idle slots give
+ * theirs up when needed), and are allocated and freed in stream order on the
+ * slot's own stream, so resizing never waits for other batches.  The device
+ * bytes actually held are reported by solve_memory.  Errors: E_ARG (null or
+ * bad config), E_DEVICE. */
 int solve_create(const solve_config *cfg, solve_ctx **out);
 
 /* Submit one curve.  knots/values: n doubles each (host or device pointers,
@@ -123,8 +129,10 @@ int solve_create(const solve_config *cfg, solve_ctx **out);
  * explicit queries: its y'' and then spline_eval_points).  *ticket_out
  * receives the request's ticket.  Errors: E_ARG, E_SIZE (n < 3, m < 1,
  * n > SOLVE_MAX_N_SOLVE), E_ORDER (the copied knots are checked before the
- * call returns), E_BUDGET (the request's resident footprint 8*(3n + m [+ m for
- * explicit queries]) + 64 bytes exceeds hbm_budget_bytes), E_STATE (context
+ * call returns), E_BUDGET (the request's footprint, 8*(3n + m [+ m for
+ * explicit queries]) + 40 bytes plus 48 bytes per work item (at most
+ * 2*((n-2)/255 + 1) + m/queries_per_tile + 1 items), plus one batch's 4096,
+ * exceeds hbm_budget_bytes), E_STATE (context
  * shutting down), E_DEVICE.  With SOLVE_PLAIN the request has completed when
  * the call returns (its ticket then polls DONE or ERROR). */
 int solve_submit(solve_ctx *ctx, const double *knots, const double *values, int64_t n,
@@ -156,6 +164,12 @@ double solve_clock(void);
  * bytes, [6] requests waiting for admission now, [7] peak requests in one
  * batch. */
 int solve_stats(solve_ctx *ctx, uint64_t out[8]);
+
+/* Device memory of a context: out[0] bytes its buffers hold now, out[1] the
+ * peak.  The held bytes exceed hbm_budget_bytes only by spare capacity an
+ * in-flight batch took while the budget had room (at most half of that
+ * batch's own buffers).  Errors: E_ARG. */
+int solve_memory(solve_ctx *ctx, uint64_t out[2]);
 
 /* Force the next batch launch to fail (host-side fault injection for tests of
  * the error path; no kernel runs for that batch).  Its tickets report ERROR. */

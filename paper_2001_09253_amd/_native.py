@@ -43,6 +43,7 @@ SIGNATURES = {
     "solve_ticket_info": (C.c_int, [_vp, _u64, C.POINTER(_d), C.POINTER(C.c_int)]),
     "solve_clock": (_d, []),
     "solve_stats": (C.c_int, [_vp, C.POINTER(_u64)]),
+    "solve_memory": (C.c_int, [_vp, C.POINTER(_u64)]),
     "solve_inject_fault": (C.c_int, [_vp]),
     "solve_destroy": (C.c_int, [_vp]),
     "spline_build": (C.c_int, [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp]),

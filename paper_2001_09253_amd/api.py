@@ -344,6 +344,12 @@ def solve_stats(ctx):
     return dict(zip(keys, list(out)))
 
 
+def solve_memory(ctx):
+    out = (C.c_uint64 * 2)()
+    _check(_native.lib().solve_memory(ctx, out), "solve_memory")
+    return {"device_bytes": int(out[0]), "peak_device_bytes": int(out[1])}
+
+
 def solve_inject_fault(ctx):
     _check(_native.lib().solve_inject_fault(ctx), "solve_inject_fault")
 

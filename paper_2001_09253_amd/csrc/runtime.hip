@@ -47,30 +47,53 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Device bytes held by a context's buffers, and their peak.
+struct Held {
+    std::atomic<uint64_t> now{0}, peak{0};
+    void add(uint64_t b) {
+        const uint64_t h = now.fetch_add(b) + b;
+        uint64_t pk = peak.load();
+        while (h > pk && !peak.compare_exchange_weak(pk, h)) {
+        }
+    }
+    void sub(uint64_t b) { now.fetch_sub(b); }
+};
+
+// A device buffer whose allocation and release are ordered on its owner's
+// stream (hipMallocAsync / hipFreeAsync): resizing one slot's buffers does
+// not wait for the batches running on the other slots.
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
-    int ensure(size_t bytes) {
-        if (bytes <= cap && p) return SOLVE_OK;
-        const size_t want = std::max(bytes, cap + cap / 2) + 256;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        if (hipMalloc(&p, want) != hipSuccess) {
+    // Reallocate to exactly `want` bytes (the old contents are dropped).
+    int resize(size_t want, hipStream_t s, Held& held) {
+        drop(s, held);
+        if (hipMallocAsync(&p, want, s) != hipSuccess) {
             p = nullptr;
             return SOLVE_E_DEVICE;
         }
         cap = want;
+        held.add(cap);
         return SOLVE_OK;
     }
-    void release() {
-        if (p) (void)hipFree(p);
+    void drop(hipStream_t s, Held& held) {
+        if (p) {
+            (void)hipFreeAsync(p, s);
+            held.sub(cap);
+        }
         p = nullptr;
         cap = 0;
     }
     template <typename T>
     T* as() const { return (T*)p; }
 };
+
+// Capacity for a buffer that must hold `bytes`: half again as much (fewer
+// reallocations as batches grow) when `room` allows it, else exactly `bytes`.
+size_t with_slack(size_t bytes, uint64_t room) {
+    const size_t want = bytes + bytes / 2 + 256;
+    return want <= room ? want : bytes;
+}
 
 struct HostBuf {  // pinned host staging
     void* p = nullptr;
@@ -146,12 +169,20 @@ struct Req {
 };
 using ReqP = std::shared_ptr<Req>;
 
-// Device footprint of one request while resident: knots, values, second
-// derivatives and results (plus its query points when explicit), and its
-// share of the work tables.
-uint64_t footprint(int64_t n, int64_t m, bool explicit_q) {
-    return 8ull * (uint64_t)(3 * n + m + (explicit_q ? m : 0)) + 64ull;
+// Device bytes one request adds to a batch's buffers: knots, values and
+// second derivatives (24 per knot), results (8 per query) and explicit query
+// points (8 per query); its offsets, end derivatives, status and flag (40);
+// and its work items, 48 bytes each: at most two per knot block of 255
+// intervals and one per share of queries_per_tile queries.
+uint64_t footprint(int64_t n, int64_t m, bool explicit_q, int64_t qpt) {
+    const uint64_t blocks = (uint64_t)(n - 2) / 255 + 1;
+    const uint64_t items = 2 * blocks + (uint64_t)m / (uint64_t)std::max<int64_t>(qpt, 1) + 1;
+    return 8ull * (uint64_t)(3 * n + m + (explicit_q ? m : 0)) + 40ull + 48ull * items;
 }
+
+// A batch's buffers beyond its requests' footprints: the 256-byte alignment
+// of its twelve regions.
+constexpr uint64_t kBatchBytes = 4096;
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -168,7 +199,7 @@ struct Slot {
     std::vector<int64_t> koff, qoff;
     std::vector<uint8_t> uniform;
     size_t o_koff = 0, o_qoff = 0, o_sd = 0, o_ed = 0, o_x = 0, o_y = 0, o_xq = 0, o_tab = 0, in_bytes = 0;
-    size_t o_status = 0, o_yq = 0, o_ypp = 0, out_bytes = 0;
+    size_t o_status = 0, o_bad = 0, o_yq = 0, o_ypp = 0, out_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void drop_graph() {
@@ -223,6 +254,8 @@ struct solve_ctx {
     std::mutex plain_mu;
     hipStream_t plain_stream = nullptr;
     DevBuf px, py, pypp, pyq, pxq, pstatus;
+    // device bytes held by the slots' and the plain path's buffers
+    Held held;
 };
 
 namespace {
@@ -268,6 +301,38 @@ void event_put(solve_ctx* c, hipEvent_t& e) {
     e = nullptr;
 }
 
+// Size slot s's device buffers for its batch (in_bytes, out_bytes) within
+// the budget: the room is the budget less what the other slots hold; idle
+// slots give up their buffers when the batch would not fit beside them.
+// Admission keeps the running batches' footprints within the budget, so the
+// bytes held exceed it only by spare capacity a running slot took earlier
+// (at most half its batch).  Scheduler thread only.
+int size_slot(solve_ctx* c, Slot& s) {
+    const uint64_t budget = c->cfg.hbm_budget_bytes;
+    const uint64_t need = s.in_bytes + s.out_bytes;
+    auto others = [&]() { return c->held.now.load() - s.din.cap - s.dout.cap; };
+    if (others() + need > budget)
+        for (auto& t : c->slots)
+            if (t.get() != &s && !t->busy) {
+                t->din.drop(t->stream, c->held);
+                t->dout.drop(t->stream, c->held);
+            }
+    const uint64_t room = budget > others() ? budget - others() : 0;
+    // spare capacity (half again) only when both buffers can have it
+    const size_t in_spare = s.in_bytes + s.in_bytes / 2 + 256, out_spare = s.out_bytes + s.out_bytes / 2 + 256;
+    const bool slack = in_spare + out_spare <= room;
+    const size_t in_want = slack ? in_spare : s.in_bytes;
+    const size_t out_want = slack ? out_spare : s.out_bytes;
+    // reallocate a buffer that is too small, or larger than it may be when
+    // the slot holds more than its room
+    const bool over = s.din.cap + s.dout.cap > room;
+    int rc = SOLVE_OK;
+    if (!s.din.p || s.din.cap < s.in_bytes || (over && s.din.cap > in_want)) rc = s.din.resize(in_want, s.stream, c->held);
+    if (!rc && (!s.dout.p || s.dout.cap < s.out_bytes || (over && s.dout.cap > out_want)))
+        rc = s.dout.resize(out_want, s.stream, c->held);
+    return rc;
+}
+
 // Stage, copy and launch one batch on slot s (called without the lock; the
 // slot is owned by the scheduler thread until its event completes).
 int launch_batch(solve_ctx* c, Slot& s) {
@@ -292,7 +357,9 @@ int launch_batch(solve_ctx* c, Slot& s) {
     nt = s.koff[count];
     mt = s.qoff[count];
     if (!s.batch) s.batch.reset(new Batch(c->cfg.device));
-    int rc = s.batch->plan(count, s.koff.data(), s.qoff.data(), c->tuning, c->cfg.precision, s.uniform.data());
+    // (host tables only: they travel in the batch's input region)
+    int rc = s.batch->plan(count, s.koff.data(), s.qoff.data(), c->tuning, c->cfg.precision, s.uniform.data(),
+                           true);
     if (rc) return rc;
     // layouts
     size_t o = 0;
@@ -307,13 +374,13 @@ int launch_batch(solve_ctx* c, Slot& s) {
     s.in_bytes = o;
     o = 0;
     s.o_status = o; o = align256(o + 4 * count);
+    s.o_bad = o;    o = align256(o + (s.batch->needs_bad() ? 4 * count : 0));
     s.o_yq = o;     o = align256(o + 8 * mt);
     s.o_ypp = o;    o = align256(o + 8 * nt);
     s.out_bytes = o;
     rc = rc ? rc : s.hin.ensure(s.in_bytes);
-    rc = rc ? rc : s.din.ensure(s.in_bytes);
     rc = rc ? rc : s.hout.ensure(s.out_bytes);
-    rc = rc ? rc : s.dout.ensure(s.out_bytes);
+    rc = rc ? rc : size_slot(c, s);
     if (rc) return rc;
     // stage the inputs
     std::memcpy(s.hin_at<int64_t>(s.o_koff), s.koff.data(), 8 * (count + 1));
@@ -348,7 +415,8 @@ int launch_batch(solve_ctx* c, Slot& s) {
     if (!rc)
         rc = s.batch->launch_with_tables(s.din_at<char>(s.o_tab), dx, dy, s.din_at<double>(s.o_sd),
                                          s.din_at<double>(s.o_ed), s.din_at<int64_t>(s.o_koff),
-                                         s.din_at<int64_t>(s.o_qoff), dyq, dypp, s.dout_at<int32_t>(s.o_status), st);
+                                         s.din_at<int64_t>(s.o_qoff), dyq, dypp, s.dout_at<int32_t>(s.o_status), st,
+                                         nullptr, s.dout_at<int32_t>(s.o_bad));
     // curves too long for the batched kernels: the single-curve kernels
     // (y'' only, and one throw-away query, when the queries are explicit)
     for (int64_t i = 0; i < count && !rc; ++i) {
@@ -419,7 +487,7 @@ std::vector<ReqP> admit_locked(solve_ctx* c) {
     std::vector<ReqP> out;
     const size_t window = 64;
     const int64_t max_batch_queries = (int64_t)1 << 27;
-    uint64_t bytes = 0;
+    uint64_t bytes = kBatchBytes;
     int64_t queries = 0;
     size_t scanned = 0;
     bool head_blocked = false;
@@ -498,7 +566,7 @@ void scheduler(solve_ctx* c) {
                 Slot& s = *free_slot;
                 s.busy = true;
                 s.reqs = std::move(reqs);
-                s.bytes = 0;
+                s.bytes = kBatchBytes;
                 const double ta = now_s();
                 for (auto& r : s.reqs) {
                     s.bytes += r->bytes;
@@ -576,12 +644,17 @@ int run_plain(solve_ctx* c, Req& r) {
     std::lock_guard<std::mutex> g(c->plain_mu);
     hipStream_t s = c->plain_stream;
     int rc = SOLVE_OK;
-    rc = rc ? rc : c->px.ensure(8 * r.n);
-    rc = rc ? rc : c->py.ensure(8 * r.n);
-    rc = rc ? rc : c->pypp.ensure(8 * r.n);
-    rc = rc ? rc : c->pyq.ensure(8 * r.m);
-    rc = rc ? rc : c->pstatus.ensure(4);
-    if (r.explicit_q()) rc = rc ? rc : c->pxq.ensure(8 * r.m);
+    // one request at a time: its buffers, with spare capacity while the
+    // budget has room for it
+    DevBuf* bufs[6] = {&c->px, &c->py, &c->pypp, &c->pyq, &c->pstatus, &c->pxq};
+    const size_t need[6] = {8 * (size_t)r.n, 8 * (size_t)r.n, 8 * (size_t)r.n, 8 * (size_t)r.m, 4,
+                            r.explicit_q() ? 8 * (size_t)r.m : 0};
+    for (int b = 0; b < 6 && !rc; ++b) {
+        if (!need[b] || (bufs[b]->p && bufs[b]->cap >= need[b])) continue;
+        const uint64_t others = c->held.now.load() - bufs[b]->cap;
+        const uint64_t room = c->cfg.hbm_budget_bytes > others ? c->cfg.hbm_budget_bytes - others : 0;
+        rc = bufs[b]->resize(with_slack(need[b], room), s, c->held);
+    }
     if (rc) return rc;
     r.t[1] = r.t[2] = now_s();
     // device outputs: after the work the caller had queued when it submitted
@@ -711,8 +784,8 @@ extern "C" int solve_submit(solve_ctx* c, const double* knots, const double* val
                 rc = SOLVE_E_ORDER;
                 break;
             }
-    r->bytes = footprint(n, m, xq != nullptr);
-    if (!rc && r->bytes > c->cfg.hbm_budget_bytes) rc = SOLVE_E_BUDGET;
+    r->bytes = footprint(n, m, xq != nullptr, c->tuning.queries_per_tile);
+    if (!rc && r->bytes + kBatchBytes > c->cfg.hbm_budget_bytes) rc = SOLVE_E_BUDGET;
     if (!rc && (r->yq_dev || r->ypp_dev)) r->ev = after;  // kept until the outputs are written
     else event_put(c, after);
     if (rc) {
@@ -800,6 +873,13 @@ extern "C" int solve_stats(solve_ctx* c, uint64_t out[8]) {
     return SOLVE_OK;
 }
 
+extern "C" int solve_memory(solve_ctx* c, uint64_t out[2]) {
+    if (!c || !out) return SOLVE_E_ARG;
+    out[0] = c->held.now.load();
+    out[1] = c->held.peak.load();
+    return SOLVE_OK;
+}
+
 extern "C" int solve_inject_fault(solve_ctx* c) {
     if (!c) return SOLVE_E_ARG;
     std::lock_guard<std::mutex> lk(c->mu);
@@ -824,14 +904,16 @@ extern "C" int solve_destroy(solve_ctx* c) {
         (void)hipStreamSynchronize(s->stream);
         s->drop_graph();
         s->batch.reset();
-        s->din.release();
-        s->dout.release();
+        s->din.drop(s->stream, c->held);
+        s->dout.drop(s->stream, c->held);
+        (void)hipStreamSynchronize(s->stream);
         s->hin.release();
         s->hout.release();
         (void)hipEventDestroy(s->done);
         (void)hipStreamDestroy(s->stream);
     }
-    for (DevBuf* d : {&c->px, &c->py, &c->pypp, &c->pyq, &c->pxq, &c->pstatus}) d->release();
+    for (DevBuf* d : {&c->px, &c->py, &c->pypp, &c->pyq, &c->pxq, &c->pstatus}) d->drop(c->plain_stream, c->held);
+    (void)hipStreamSynchronize(c->plain_stream);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->plain_stream);
     (void)hipStreamDestroy(c->in_stream);

@@ -150,6 +150,7 @@ def replay(trace: workloads.Trace, reqs: list[Request], *, plain: bool = False, 
     for t in th:
         t.join()
     stats = api.solve_stats(ctx)
+    stats.update(api.solve_memory(ctx))
     api.solve_destroy(ctx)
     if failure:
         raise failure[0]

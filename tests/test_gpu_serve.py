@@ -242,15 +242,48 @@ def test_admission_under_a_small_budget():
     try:
         sts, res = run_all(ctx, reqs)
         stats = api.solve_stats(ctx)
+        mem = api.solve_memory(ctx)
     finally:
         api.solve_destroy(ctx)
     assert all(s == api.DONE for s in sts)
     assert stats["completed"] == len(reqs)
     assert stats["peak_resident_bytes"] <= budget
     assert stats["batches"] > 1
+    # the device buffers the slots held: within the budget, but for spare
+    # capacity a running batch took while there was room (half its buffers)
+    assert 0 < mem["peak_device_bytes"] <= budget + budget // 2
     for r in (0, 17, 60, 119):
         o_yq, o_ypp = expected(reqs[r])
         assert_close(res[r][0], o_yq, "budget yq %d" % r)
+
+
+@pytest.mark.parametrize("flags", [0, api.PLAIN])
+def test_device_memory_within_the_budget(flags):
+    # many small requests (the slots' buffers grow with spare capacity while
+    # the budget has room), then large ones that need the room: idle slots
+    # give theirs up and the buffers are sized exactly
+    small = [(13, 2048)] * 40
+    large = [(1300, 204800)] * 6 + [(700, 90)] * 3
+    reqs = make_reqs(11, small + large)
+    big = 8 * (3 * 1300 + 204800)
+    budget = 3 * big
+    ctx = api.solve_create(hbm_budget_bytes=budget, max_inflight=3, flags=flags)
+    try:
+        sts, res = run_all(ctx, reqs[:40])
+        mem_small = api.solve_memory(ctx)
+        sts2, res2 = run_all(ctx, reqs[40:])
+        mem = api.solve_memory(ctx)
+    finally:
+        api.solve_destroy(ctx)
+    assert all(s == api.DONE for s in sts + sts2)
+    assert 0 < mem_small["device_bytes"] <= budget
+    assert mem["peak_device_bytes"] <= budget + budget // 2
+    assert mem["device_bytes"] <= budget + budget // 2
+    for r in (0, 39, 40, 45, 48):
+        o_yq, o_ypp = expected(reqs[r])
+        got = (res + res2)[r]
+        assert_close(got[0], o_yq, "memory yq %d" % r)
+        assert_close(got[1], o_ypp, "memory ypp %d" % r)
 
 
 def test_slot_limit_and_continuous_batching():
