@@ -98,16 +98,20 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
         }
         __syncthreads();
         if (tid < 2) {
-            // intervals of the tile's smallest and largest query
+            // intervals of the tile's smallest and largest query; a NaN query
+            // has no place in the order, and its tile searches everything
+            // (the flag travels in win[0], which no thread writes again
+            // before every thread has passed the next tile's barriers, while
+            // nan_any is cleared before the first of them)
             double v = sm.red[tid * NW];
             for (int w = 1; w < NW; ++w) v = tid == 0 ? fmin(v, sm.red[w]) : fmax(v, sm.red[NW + w]);
-            sm.win[tid] = clip_interval(count_below_fenced(x, n, sm.fence, nf, stride, v), n);
+            const int64_t iv = clip_interval(count_below_fenced(x, n, sm.fence, nf, stride, v), n);
+            sm.win[tid] = (tid == 0 && sm.nan_any) ? -1 : iv;
         }
         __syncthreads();
         const int64_t ilo = sm.win[0];
         const int64_t ihi = max(sm.win[1], ilo);
-        // a NaN query has no place in the order: the tile searches everything
-        const bool staged = !sm.nan_any && ihi - ilo + 2 <= kPointWin;
+        const bool staged = ilo >= 0 && ihi - ilo + 2 <= kPointWin;
         if (staged) {
             const int W = (int)(ihi - ilo) + 2;
             for (int t = tid; t < W; t += BLOCK) {
@@ -202,9 +206,7 @@ static int launch_points_t(const double* x, const double* y, const double* ypp, 
     const int nf = (int)((n + stride - 1) / stride);
     const int64_t tiles = (m + Q - 1) / Q;
     // one round of resident workgroups (5 per compute unit: 29 KB of LDS each)
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * 5));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * 5));
     eval_points_kernel<kEvalBlock, QPT, DERIVS, IDX><<<(unsigned)grid, kEvalBlock, 0, s>>>(x, y, ypp, n, xq, m, yq, d1,
                                                                                            d2, idx, stride, nf);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;

@@ -18,4 +18,7 @@ int launch_eval_points(const double* x, const double* y, const double* ypp, int6
 int launch_solve_uniform(const double* x, const double* y, int64_t n, double sd, double ed, int64_t m, double* yq,
                          double* ypp, int32_t* status, int32_t* idx, hipStream_t s);
 
+// Compute units of the current device (looked up once per device).
+int device_cu_count();
+
 }  // namespace spl

@@ -814,6 +814,8 @@ static int cu_count() {
     return v;
 }
 
+int device_cu_count() { return cu_count(); }
+
 // Workgroups of `kernel` (of `threads` threads) one compute unit holds at once.
 template <typename K>
 static int resident_per_cu(std::atomic<int>* cache, K kernel, int threads) {

@@ -170,7 +170,7 @@ def test_deterministic_repeat():
         np.testing.assert_array_equal(yq_k, outs[0][1])
 
 
-@pytest.mark.parametrize("kind", ["random", "sorted", "outside", "on_knots", "nan"])
+@pytest.mark.parametrize("kind", ["random", "sorted", "outside", "on_knots", "nan", "nan_sorted"])
 def test_eval_points_matches_oracle(kind):
     n = 777
     x, y = w.paper_curve(np.random.default_rng(11), n)
@@ -185,9 +185,15 @@ def test_eval_points_matches_oracle(kind):
         q = rng.uniform(x[0] - 5, x[-1] + 5, 5000)
     elif kind == "on_knots":
         q = np.concatenate([x, np.nextafter(x, np.inf), np.nextafter(x, -np.inf)])
-    else:
+    elif kind == "nan":
         q = rng.uniform(x[0], x[-1], 3000)
         q[17] = np.nan
+    else:
+        # sorted points (tiles of 2048 whose knots fit the staged window)
+        # with a NaN in every third tile: those tiles search everything,
+        # their neighbours stay staged
+        q = np.sort(rng.uniform(x[0], x[-1], 40000))
+        q[np.arange(5, len(q), 3 * 2048)] = np.nan
     m = len(q)
     qd = dev(q)
     yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
