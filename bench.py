@@ -777,8 +777,9 @@ def main():
                     help="batched: measured seconds of each served path in the context")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the spline path is measured on one MI355X "
-              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the spline path runs on one MI355X, and how it "
+              "would shard is a design note, not a code path (--gpus %d is not supported)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == "plain":
         out = bench_single(args, 13000, 2048000, "plain: 1 curve, n=13000, m=2048000 uniform queries")
