@@ -38,8 +38,10 @@ __global__ __launch_bounds__(BLOCK) void eval_uniform_kernel(const double* __res
 // sorted, or clustered) the window's knots, values and y'' are staged and
 // every query searches the window, else every query searches the fence
 // table and then global memory.
-constexpr int kFenceMax = 2048;  // fences in LDS (16 KB)
+constexpr int kFenceMax = 8192;  // fences in LDS (64 KB): every knot up to 8192 knots
 constexpr int kPointWin = 512;   // staged window, in knots
+constexpr int kPointBlock = 512;  // threads of a workgroup
+constexpr int kPointGroups = 2;   // workgroups per compute unit (77 KB of LDS each)
 
 template <int BLOCK>
 struct PointSmem {
@@ -201,14 +203,14 @@ template <bool DERIVS, bool IDX>
 static int launch_points_t(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
                            int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s) {
     constexpr int QPT = 8;
-    constexpr int64_t Q = (int64_t)kEvalBlock * QPT;
+    constexpr int64_t Q = (int64_t)kPointBlock * QPT;
     const int64_t stride = std::max<int64_t>(1, (n + kFenceMax - 1) / kFenceMax);
     const int nf = (int)((n + stride - 1) / stride);
     const int64_t tiles = (m + Q - 1) / Q;
-    // one round of resident workgroups (5 per compute unit: 29 KB of LDS each)
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * 5));
-    eval_points_kernel<kEvalBlock, QPT, DERIVS, IDX><<<(unsigned)grid, kEvalBlock, 0, s>>>(x, y, ypp, n, xq, m, yq, d1,
-                                                                                           d2, idx, stride, nf);
+    // one round of resident workgroups
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * kPointGroups));
+    eval_points_kernel<kPointBlock, QPT, DERIVS, IDX><<<(unsigned)grid, kPointBlock, 0, s>>>(x, y, ypp, n, xq, m, yq,
+                                                                                             d1, d2, idx, stride, nf);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
 }
 

@@ -3,8 +3,8 @@ checked against the definition of the interval (section 2: the interval of q
 is the last knot interval starting below q, clipped to the first and last
 interval), by brute force.
 
-The kernel keeps every stride-th knot as a fence (at most 2048 fences,
-stride = ceil(n / 2048)); with c fences below q, every knot below index
+The kernel keeps every stride-th knot as a fence (at most 8192 fences,
+stride = ceil(n / 8192)); with c fences below q, every knot below index
 (c - 1) * stride + 1 is below q and none from c * stride on is, so a lower
 bound over that one stretch of knots completes the count. A tile of queries
 whose smallest and largest query fall in intervals ilo .. ihi with
@@ -18,7 +18,7 @@ import math
 import numpy as np
 import pytest
 
-FENCE_MAX = 2048
+FENCE_MAX = 8192
 WIN = 512
 
 
@@ -72,7 +72,7 @@ def queries(x, rng, count):
          np.nextafter(hi, np.inf)]])
 
 
-@pytest.mark.parametrize("n", [3, 4, 5, 64, 2047, 2048, 2049, 4095, 4096, 4097, 6145, 100003])
+@pytest.mark.parametrize("n", [3, 4, 5, 64, 2047, 2048, 2049, 8191, 8192, 8193, 13000, 16385, 24577, 100003])
 def test_fenced_count_is_the_definition(n):
     rng = np.random.default_rng(n)
     x = knots(n, rng)
@@ -104,7 +104,7 @@ def staged_tile(x, fence, stride, tile):
     return staged, out
 
 
-@pytest.mark.parametrize("n", [3, 5, 513, 2049, 100003])
+@pytest.mark.parametrize("n", [3, 5, 513, 8193, 100003])
 def test_staged_window_is_the_definition(n):
     rng = np.random.default_rng(7 + n)
     x = knots(n, rng)
