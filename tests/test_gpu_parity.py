@@ -189,11 +189,11 @@ def test_eval_points_matches_oracle(kind):
         q = rng.uniform(x[0], x[-1], 3000)
         q[17] = np.nan
     else:
-        # sorted points (tiles of 2048 whose knots fit the staged window)
+        # sorted points (tiles of 4096 whose knots fit the staged window)
         # with a NaN in every third tile: those tiles search everything,
         # their neighbours stay staged
-        q = np.sort(rng.uniform(x[0], x[-1], 40000))
-        q[np.arange(5, len(q), 3 * 2048)] = np.nan
+        q = np.sort(rng.uniform(x[0], x[-1], 60000))
+        q[np.arange(5, len(q), 3 * 4096)] = np.nan
     m = len(q)
     qd = dev(q)
     yq = torch.full((m,), np.nan, dtype=torch.float64, device="cuda")
