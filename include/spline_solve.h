@@ -98,6 +98,10 @@ typedef struct {
  * start_deriv, end_deriv), plus the points to interpolate at).
  * ========================================================================== */
 
+/* Every call below but solve_destroy may be made from several host threads
+ * at once on one context (submissions, polls and waits are serialised
+ * internally); solve_destroy must not overlap another call on its context. */
+
 /* Create a context on cfg->device.  *out receives an owned handle that must be
  * released with solve_destroy.  A background scheduler thread admits
  * requests against hbm_budget_bytes / max_slots and launches them in fused

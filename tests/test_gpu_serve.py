@@ -3,6 +3,7 @@ results against the FP64 oracle, the same result alone and inside a mix,
 admission under a small HBM budget, error paths, and an open-loop Poisson
 replay through both the batched and the plain path."""
 import ctypes as C
+import threading
 
 import numpy as np
 import pytest
@@ -284,6 +285,49 @@ def test_device_memory_within_the_budget(flags):
         got = (res + res2)[r]
         assert_close(got[0], o_yq, "memory yq %d" % r)
         assert_close(got[1], o_ypp, "memory ypp %d" % r)
+
+
+@pytest.mark.parametrize("flags", [0, api.PLAIN])
+def test_concurrent_submitters(flags):
+    # four host threads submit and wait on one context at once (the ctypes
+    # calls release the interpreter lock); every result is the oracle's
+    rng = np.random.default_rng(41)
+    sizes = [(int(n), int(m)) for n, m in zip(rng.integers(3, 3000, 160), rng.integers(1, 60000, 160))]
+    reqs = make_reqs(41, sizes, explicit=set(range(0, 160, 9)))
+    outs = [None] * len(reqs)
+    errors = []
+    ctx = api.solve_create(flags=flags, max_inflight=3)
+
+    def worker(w):
+        try:
+            mine = list(range(w, len(reqs), 4))
+            tickets = []
+            for r in mine:
+                x, y, sd, ed, xq, m = reqs[r]
+                yq, ypp = np.full(m, np.nan), np.full(len(x), np.nan)
+                tickets.append(api.solve_submit(ctx, x, y, sd, ed, xq, m, yq, ypp))
+                outs[r] = (yq, ypp)
+            for t in tickets:
+                assert api.solve_wait(ctx, t) == api.DONE
+                assert api.solve_poll(ctx, t) == api.DONE
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    try:
+        threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        stats = api.solve_stats(ctx)
+    finally:
+        api.solve_destroy(ctx)
+    assert not errors, errors
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for r in range(len(reqs)):
+        o_yq, o_ypp = expected(reqs[r])
+        assert_close(outs[r][1], o_ypp, "concurrent ypp %d" % r)
+        assert_close(outs[r][0], o_yq, "concurrent yq %d" % r)
 
 
 def test_slot_limit_and_continuous_batching():
