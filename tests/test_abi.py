@@ -82,6 +82,35 @@ def test_argument_errors_need_no_device(lib):
     assert lib.spline_plan_create(0, 1, None, koff.ctypes.data_as(C.c_void_p), 0, None, C.byref(out)) == api.E_ARG
 
 
+def test_every_handle_call_rejects_a_null_handle(lib):
+    """Each call on a context or a plan checks its handle (and its output
+    pointers) before it touches the device."""
+    p = C.c_void_p(0x1000)
+    u64 = (C.c_uint64 * 8)()
+    st = C.c_int()
+    tk = C.c_uint64()
+    t4 = (C.c_double * 4)()
+    i64 = C.c_int64()
+    tun = _native.Tuning()
+    ms = C.c_double()
+    assert lib.solve_submit(None, p, p, 10, 0.0, 0.0, None, 5, p, None, C.byref(tk)) == api.E_ARG
+    assert lib.solve_wait(None, 1, C.byref(st), 0) == api.E_ARG
+    assert lib.solve_ticket_info(None, 1, t4, None) == api.E_ARG
+    assert lib.solve_stats(None, u64) == api.E_ARG
+    assert lib.solve_memory(None, u64) == api.E_ARG
+    assert lib.solve_inject_fault(None) == api.E_ARG
+    assert lib.spline_plan_run(None, *([p] * 10)) == api.E_ARG
+    assert lib.spline_plan_run_indexed(None, *([p] * 11)) == api.E_ARG
+    assert lib.spline_plan_capture(None, *([p] * 10)) == api.E_ARG
+    assert lib.spline_plan_get_tuning(None, C.byref(tun)) == api.E_ARG
+    assert lib.spline_plan_get_tables(None, None, 0, C.byref(i64), C.byref(i64), C.byref(i64)) == api.E_ARG
+    assert lib.spline_plan_autotune(None, *([p] * 8), 1, None, C.byref(tun), C.byref(ms)) == api.E_ARG
+    assert lib.spline_batch_run_noalloc(1, None, p, 0, None, *([p] * 10)) == api.E_ARG
+    assert lib.spline_solve_uniform_indexed(p, p, 10, 0.0, 0.0, 5, p, None, None, None, None) == api.E_ARG
+    assert lib.spline_solve_uniform_indexed(p, p, 2, 0.0, 0.0, 5, p, None, p, None, None) == api.E_SIZE
+    assert lib.spline_solve_uniform_indexed(p, p, 10, 0.0, 0.0, 0, p, None, p, None, None) == api.E_SIZE
+
+
 def test_create_rejects_bad_config(lib):
     cfg = _native.SolveConfig(0, 0, 16, 0, 0, 2, None)     # zero budget
     h = C.c_void_p()
