@@ -50,8 +50,8 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void group_build_ker
 }
 
 // ---------------------------------------------------------------------------
-// Phase 1 in mixed precision (SOLVE_FP32_REFINE): one wavefront per curve.
-// The rows of a1-a2 are formed in FP64 (all lanes); the paper's forward
+// Phase 1 in mixed precision (SOLVE_FP32_REFINE) for the curves past
+// kLaneBuildMaxN knots: one wavefront per curve.  The rows of a1-a2 are formed in FP64 (all lanes); the paper's forward
 // elimination and back substitution run in FP32 over them (lane 0); then
 // REFINE times the FP64 residual d - T y'' of the same rows is formed (all
 // lanes) and the FP32 sweeps solve for its correction (lane 0), which is added
@@ -169,6 +169,285 @@ __global__ __launch_bounds__(kWave) void mixed_build_kernel(BatchDevArgs a) {
         wave_sync();
     }
     for (int j = lane; j < n; j += kWave) a.ypp[ko + j] = sm.yh[j];
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1 in mixed precision, lane-parallel, for the curves of at most
+// kLaneBuildMaxN knots: kGroupLanes lanes per curve (one DPP row, four curves
+// per wavefront), each lane owning up to CH consecutive rows.  The FP32 solver
+// is the paper's elimination with its three recurrences split over the lanes'
+// chunks and joined by scans inside the row:
+//   pivots   c'_j = c_j / (b_j - a_j c'_{j-1}): a projective map of (P, Q)
+//            (c' = P/Q) per row, the matrix [[0, c], [-a, b]];
+//   forward  d'_j = (r_j - a_j d'_{j-1}) / (b_j - a_j c'_{j-1}): affine in d';
+//   backward y_j = d'_j - c'_j y_{j+1}: affine in y.
+// The pivots are factored once; each of the 1 + kRefineSteps right-hand sides
+// (d, then the FP64 residuals d - T y'') takes one forward and one backward
+// scan.  The rows are formed in FP64 and rounded to FP32; residuals and the
+// updates of y'' are FP64, the neighbouring lanes' y'' taken by DPP.
+// ---------------------------------------------------------------------------
+struct Mob32 {  // (P, Q) -> (m00 P + m01 Q, m10 P + m11 Q)
+    float m00, m01, m10, m11;
+};
+struct Aff32 {  // v -> K v + H
+    float K, H;
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Scale by a power of two (exact) so that the largest entry lies in [0.5, 1);
+// c' = P/Q does not change.
+__device__ __forceinline__ Mob32 mob_normalize(Mob32 o) {
+    const float mx = fmaxf(fmaxf(fabsf(o.m00), fabsf(o.m01)), fmaxf(fabsf(o.m10), fabsf(o.m11)));
+    if (mx > 0.0f && mx < __builtin_inff()) {
+        int e = 0;
+        (void)frexpf(mx, &e);
+        o.m00 = ldexpf(o.m00, -e);
+        o.m01 = ldexpf(o.m01, -e);
+        o.m10 = ldexpf(o.m10, -e);
+        o.m11 = ldexpf(o.m11, -e);
+    }
+    return o;
+}
+
+// B applied after A.
+__device__ __forceinline__ Mob32 mob_compose(const Mob32& B, const Mob32& A) {
+    return mob_normalize(Mob32{B.m00 * A.m00 + B.m01 * A.m10, B.m00 * A.m01 + B.m01 * A.m11,
+                               B.m10 * A.m00 + B.m11 * A.m10, B.m10 * A.m01 + B.m11 * A.m11});
+}
+
+// Outer applied to the result of inner.
+__device__ __forceinline__ Aff32 aff_compose(const Aff32& O, const Aff32& I) {
+    return Aff32{O.K * I.K, O.K * I.H + O.H};
+}
+
+template <int CTRL>
+__device__ __forceinline__ Mob32 dpp_mob(const Mob32& v) {
+    return Mob32{dpp_f32<CTRL>(1.0f, v.m00), dpp_f32<CTRL>(0.0f, v.m01), dpp_f32<CTRL>(0.0f, v.m10),
+                 dpp_f32<CTRL>(1.0f, v.m11)};
+}
+template <int CTRL>
+__device__ __forceinline__ Aff32 dpp_aff(const Aff32& v) {
+    return Aff32{dpp_f32<CTRL>(1.0f, v.K), dpp_f32<CTRL>(0.0f, v.H)};
+}
+
+// Exclusive scans inside each row of 16 lanes: the prefix composes the lanes
+// before (inner) with later lanes outer, the suffix the lanes after (inner);
+// a lane with nothing before (after) it gets the identity.
+__device__ __forceinline__ Mob32 row_excl_prefix_mob(Mob32 v) {
+    v = mob_compose(v, dpp_mob<kDppRowShr1>(v));
+    v = mob_compose(v, dpp_mob<kDppRowShr2>(v));
+    v = mob_compose(v, dpp_mob<kDppRowShr4>(v));
+    v = mob_compose(v, dpp_mob<kDppRowShr8>(v));
+    return dpp_mob<kDppRowShr1>(v);
+}
+__device__ __forceinline__ Aff32 row_excl_prefix_aff(Aff32 v) {
+    v = aff_compose(v, dpp_aff<kDppRowShr1>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShr2>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShr4>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShr8>(v));
+    return dpp_aff<kDppRowShr1>(v);
+}
+__device__ __forceinline__ Aff32 row_excl_suffix_aff(Aff32 v) {
+    v = aff_compose(v, dpp_aff<kDppRowShl1>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShl2>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShl4>(v));
+    v = aff_compose(v, dpp_aff<kDppRowShl8>(v));
+    return dpp_aff<kDppRowShl1>(v);
+}
+
+template <int CH>
+__global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_build_kernel(BatchDevArgs a) {
+    __shared__ double lds_x[kGroupsPerBlock][kGroupLanes * CH];
+    __shared__ double lds_y[kGroupsPerBlock][kGroupLanes * CH];
+    const int grp = threadIdx.x / kGroupLanes;
+    const int gl = threadIdx.x & (kGroupLanes - 1);
+    const int64_t slot = (int64_t)blockIdx.x * kGroupsPerBlock + grp;
+    const bool has = slot < a.n_lane;  // groups past the list run with no rows
+    const int i = has ? a.lane_curves[slot] : 0;
+    const int64_t ko = has ? a.koff[i] : 0;
+    const int n = has ? (int)(a.koff[i + 1] - ko) : 0;
+    const double sd = has ? a.sd[i] : 0.0;
+    const double ed = has ? a.ed[i] : 0.0;
+    const bool nat_s = natural_end(sd);
+    const bool nat_e = natural_end(ed);
+    double* sl = lds_x[grp];
+    double* sv = lds_y[grp];
+    // rows s .. s + cnt - 1 are this lane's (n <= kGroupLanes * CH)
+    const int r = (n + kGroupLanes - 1) / kGroupLanes;
+    const int s = gl * r;
+    const int cnt = max(0, min(n, s + r) - s);
+
+    // a1: knots and values staged through the LDS in one load round
+    for (int j = gl; j < n; j += kGroupLanes) {
+        sl[j] = a.x[ko + j];
+        sv[j] = a.y[ko + j];
+    }
+    wave_sync();
+    // widths and validation
+    bool bad = false;
+    double w[CH];
+    double wprev0 = 0.0;
+    {
+        double xprev = (cnt > 0 && s >= 1) ? sl[s - 1] : 0.0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            w[k] = 0.0;
+            if (k < cnt) {
+                const int j = s + k;
+                const double xj = sl[j];
+                if (j >= 1 && !(xj > xprev)) bad = true;
+                if (k == 0) wprev0 = (j >= 1) ? xj - xprev : 0.0;
+                w[k] = (j + 1 < n) ? sl[j + 1] - xj : 0.0;
+                xprev = xj;
+            }
+        }
+    }
+    bad = group_any<true, kGroupLanes>(bad);
+    // a1/a2: slopes and right-hand sides (FP64)
+    double d[CH];
+    {
+        double sprev = (cnt > 0 && s >= 1) ? (sv[s] - sv[s - 1]) * fast_rcp(wprev0) : 0.0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            d[k] = 0.0;
+            if (k < cnt) {
+                const int j = s + k;
+                const double snext = (j + 1 < n) ? (sv[j + 1] - sv[j]) * fast_rcp(w[k]) : 0.0;
+                if (j == 0) d[k] = nat_s ? 0.0 : 6.0 * (snext - sd);
+                else if (j == n - 1) d[k] = nat_e ? 0.0 : 6.0 * (ed - sprev);
+                else d[k] = 6.0 * (snext - sprev);
+                sprev = snext;
+            }
+        }
+    }
+
+    // FP32 pivots: each lane's chunk map of the c' recurrence (rows scaled by
+    // 2^-e, e the exponent of b, so that the entries grow by at most 1.5 a
+    // row), the scan, then the recurrence from the entering c'
+    float cp[CH], g[CH], rf[CH], t[CH];
+    {
+        Mob32 acc{1.0f, 0.0f, 0.0f, 1.0f};
+        double wa = wprev0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) {
+                double ra, rb, rc;
+                row_coeffs(s + k, n, nat_s, nat_e, wa, w[k], &ra, &rb, &rc);
+                int e;
+                (void)frexp(rb, &e);
+                const float fa = (float)ldexp(ra, -e), fb = (float)ldexp(rb, -e), fc = (float)ldexp(rc, -e);
+                acc = Mob32{fc * acc.m10, fc * acc.m11, fb * acc.m10 - fa * acc.m00, fb * acc.m11 - fa * acc.m01};
+                wa = w[k];
+            }
+        }
+        const Mob32 pre = row_excl_prefix_mob(mob_normalize(acc));
+        float cpv = pre.m01 / pre.m11;
+        wa = wprev0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) cp[k] = g[k] = rf[k] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) {
+                double ra, rb, rc;
+                row_coeffs(s + k, n, nat_s, nat_e, wa, w[k], &ra, &rb, &rc);
+                const float fa = (float)ra, fb = (float)rb, fc = (float)rc;
+                const float inv = 1.0f / (fb - fa * cpv);
+                cpv = fc * inv;
+                cp[k] = cpv;
+                g[k] = -fa * inv;
+                rf[k] = inv;
+                wa = w[k];
+            }
+        }
+    }
+
+    double yh[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        yh[k] = 0.0;
+        t[k] = (float)d[k];
+    }
+    for (int step = 0; step <= kRefineSteps; ++step) {
+        // forward: d'_j = g_j d'_{j-1} + r_j / piv_j
+        Aff32 f{1.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) f = Aff32{g[k] * f.K, g[k] * f.H + t[k] * rf[k]};
+        }
+        float dp = row_excl_prefix_aff(f).H;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) {
+                dp = t[k] * rf[k] + g[k] * dp;
+                t[k] = dp;
+            }
+        }
+        // backward: y_j = d'_j - c'_j y_{j+1} (c' of the last row is zero)
+        Aff32 bk{1.0f, 0.0f};
+#pragma unroll
+        for (int k = CH - 1; k >= 0; --k) {
+            if (k < cnt) bk = aff_compose(Aff32{-cp[k], t[k]}, bk);
+        }
+        float yv = row_excl_suffix_aff(bk).H;
+#pragma unroll
+        for (int k = CH - 1; k >= 0; --k) {
+            if (k < cnt) {
+                yv = t[k] - cp[k] * yv;
+                t[k] = yv;
+            }
+        }
+        // the correction, added in FP64
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) yh[k] += (double)t[k];
+        }
+        if (step == kRefineSteps) break;
+        // the next right-hand side: the FP64 residual d - T y'' of the same
+        // rows, with the y'' on either side of the chunk from the neighbours
+        double ylast = 0.0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k == cnt - 1) ylast = yh[k];
+        }
+        const double yleft = dpp_f64<kDppRowShr1, 0xf>(0.0, ylast);
+        const double yright = dpp_f64<kDppRowShl1, 0xf>(0.0, yh[0]);
+        double wa = wprev0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (k < cnt) {
+                const int j = s + k;
+                double ra, rb, rc;
+                row_coeffs(j, n, nat_s, nat_e, wa, w[k], &ra, &rb, &rc);
+                double tv = rb * yh[k];
+                // (register indices stay constant after unrolling)
+                const double ym = k == 0 ? yleft : yh[k > 0 ? k - 1 : 0];
+                const double yp = k + 1 < cnt ? yh[k + 1 < CH ? k + 1 : k] : yright;
+                if (j > 0) tv += ra * ym;
+                if (j + 1 < n) tv += rc * yp;
+                t[k] = (float)(d[k] - tv);
+                wa = w[k];
+            }
+        }
+    }
+
+    // y'' staged through the LDS (every lane is done with the knots) and
+    // stored coalesced; NaN for a curve with unordered knots
+    const double nan = __builtin_nan("");
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        if (k < cnt) sl[s + k] = bad ? nan : yh[k];
+    }
+    wave_sync();
+    for (int j = gl; j < n; j += kGroupLanes) a.ypp[ko + j] = sl[j];
+    if (has && gl == 0) {
+        a.bad[i] = bad ? 1 : 0;
+        if (a.status) a.status[i] = bad ? kStatusOrder : kStatusOk;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -755,6 +1034,8 @@ void Batch::make_tables() {
         }
     }
     std::stable_sort(lane_.begin(), lane_.end(), [&](int32_t p, int32_t q) { return n_[p] > n_[q]; });
+    lane_long_ = 0;
+    while (lane_long_ < (int64_t)lane_.size() && n_[lane_[lane_long_]] > kLaneBuildMaxN) ++lane_long_;
     // phase 2: whole curves when they fit one wavefront's rows, else knot
     // blocks (with halos when the item solves its own span); shares of at
     // most about queries_per_tile queries
@@ -918,8 +1199,22 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     if (a.n_lane > 0) {
         if (!a.bad) return SOLVE_E_ARG;
         if (mixed) {
-            if (lane_max_n_ <= 256) mixed_build_kernel<256><<<(unsigned)a.n_lane, kWave, 0, s>>>(a);
-            else mixed_build_kernel<SOLVE_MAX_N_BATCH><<<(unsigned)a.n_lane, kWave, 0, s>>>(a);
+            // the curves past kLaneBuildMaxN knots (first in the list): one
+            // wavefront each; the others kGroupLanes lanes each
+            if (lane_long_ > 0) mixed_build_kernel<SOLVE_MAX_N_BATCH><<<(unsigned)lane_long_, kWave, 0, s>>>(a);
+            if (a.n_lane > lane_long_) {
+                BatchDevArgs b = a;
+                b.lane_curves += lane_long_;
+                b.n_lane = a.n_lane - lane_long_;
+                const unsigned g = (unsigned)((b.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
+                const int64_t short_max = n_[lane_[lane_long_]];
+                if (short_max <= kGroupLanes * 4)
+                    mixed_group_build_kernel<4><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
+                else if (short_max <= kGroupLanes * 9)
+                    mixed_group_build_kernel<9><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
+                else
+                    mixed_group_build_kernel<16><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
+            }
         } else {
             const unsigned g = (unsigned)((a.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
             const int64_t lane_max = lane_max_n_;

@@ -129,6 +129,7 @@ private:
     std::vector<WaveItem> witems_;
     std::vector<int32_t> lane_;
     int64_t lane_max_n_ = 0;
+    int64_t lane_long_ = 0;  // leading lane_ entries past kLaneBuildMaxN knots
     int64_t prebuilt_max_n_ = 0;
     void* d_bad_ = nullptr;
     size_t cap_bad_ = 0;

@@ -263,6 +263,26 @@ def test_mixed_precision_within_stated_error(small_batch, small_batch_oracle, tu
     assert e_yq.max() > 1e-12
 
 
+@pytest.mark.parametrize("top", [3, 64, 65, 144, 145, 256, 257])
+def test_mixed_precision_each_group_width(top):
+    """The grouped FP32 build at each of its widths (4, 9 or 16 rows per lane,
+    chosen by the batch's longest curve of at most 256 knots), every end
+    condition, curves from 3 knots up to the top size; with top = 257 one
+    curve goes to the one-wavefront build and the rest to the grouped one."""
+    rng = np.random.default_rng(top)
+    n = np.concatenate([[3, 4, 5, top, top], rng.integers(3, top + 1, 59)]).astype(np.int64)
+    m = rng.integers(1, 3000, len(n)).astype(np.int64)
+    b = w.batch_from_sizes(100 + top, n, m)
+    o = oracle.batch_uniform(b.koff, b.qoff, b.x, b.y, b.sd, b.ed)
+    plan = api.spline_plan_create(b.koff, b.qoff, precision=api.FP32_REFINE)
+    bufs, st = to_dev(b)
+    api.spline_plan_run(plan, bufs, st)
+    assert np.all(host(st) == 0)
+    e_yq, e_ypp = mixed_errors(b, host(bufs["yq"]), host(bufs["ypp"]), o)
+    assert e_ypp.max() <= MIXED_YPP_TOL, (top, e_ypp.max())
+    assert e_yq.max() <= MIXED_YQ_TOL, (top, e_yq.max())
+
+
 def test_mixed_precision_long_curves_and_bad_knots():
     n = np.array([3, 13, 300, 1000, api.MAX_N_BATCH, 130], dtype=np.int64)
     m = np.array([5, 2048, 40000, 7, 100000, 20480], dtype=np.int64)

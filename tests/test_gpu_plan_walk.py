@@ -31,18 +31,24 @@ def walk(koff, qoff, precision, tuning):
     assert rows in (64, 128, 192, 256, 512)
     ch = rows // 64
     # the first launch builds the curves of up to LANE_BUILD_MAX knots with
-    # tuning fused = 2 (16 lanes per curve), every curve in mixed precision
-    # (one wavefront per curve, the FP32 sweeps and FP64 refinement)
+    # tuning fused = 2 (16 lanes per curve), every curve in mixed precision:
+    # those past LANE_BUILD_MAX knots one wavefront each (LDS arrays of
+    # MAX_N_BATCH rows), the others 16 lanes each, as in the FP64 form
     mixed = precision == api.FP32_REFINE
     prebuilt = api.MAX_N_BATCH if mixed else LANE_BUILD_MAX if t.fused == 2 else 0
     assert sorted(lane.tolist()) == [i for i in range(count) if n[i] <= prebuilt]
     if len(lane):
         assert np.all(np.diff(n[lane]) <= 0), "first-launch curves are sorted by length"
-        if mixed:  # the curve's rows held in LDS arrays of 256 or 2048
-            assert n[lane].max() <= (256 if n[lane].max() <= 256 else api.MAX_N_BATCH)
-        else:
-            lane_ch = 4 if n[lane].max() <= GROUP_LANES * 4 else 9 if n[lane].max() <= GROUP_LANES * 9 else 16
-            assert n[lane].max() <= GROUP_LANES * lane_ch  # the group's LDS rows (16 CH + 2)
+        grouped = n[lane][n[lane] <= LANE_BUILD_MAX]
+        if mixed:
+            assert n[lane].max() <= api.MAX_N_BATCH
+            # the long ones lead the list: the one-wavefront launch takes
+            # slots 0 .. n_long - 1, the grouped launch the rest
+            n_long = int(np.count_nonzero(n[lane] > LANE_BUILD_MAX))
+            assert np.all(n[lane][:n_long] > LANE_BUILD_MAX) and np.all(n[lane][n_long:] <= LANE_BUILD_MAX)
+        if len(grouped):
+            lane_ch = 4 if grouped.max() <= GROUP_LANES * 4 else 9 if grouped.max() <= GROUP_LANES * 9 else 16
+            assert grouped.max() <= GROUP_LANES * lane_ch  # the group's LDS rows (16 CH + 2)
     # item fields against the offsets
     inst = items["inst"].astype(np.int64)
     assert np.all((inst >= 0) & (inst < count))
