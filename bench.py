@@ -20,6 +20,11 @@ Workloads (--workload):
   plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
   points   1 curve, n = 13,000, m = 2^27 explicit queries (random, or
            --sorted), with first and second derivatives (spline_eval_points)
+  batched_points
+           the batched workload's 4096 curves, each at its own explicit
+           points (as many as its uniform queries, uniform over its range,
+           random order): a build-only plan, then spline_batch_eval_points,
+           values only, inputs and outputs rotated over >= 2 GiB
   long     1 curve, n = m = 2^28 (the size sweep's largest point: one query
            per interval, the streaming kernel)
   mixed    the batched workload with the FP32 solve + FP64 refinement
@@ -484,6 +489,124 @@ def bench_points(args, sorted_queries):
     return out
 
 
+def bench_batched_points(args):
+    """The explicit variant of the batched workload: C3's 4096 curves, each
+    evaluated at its own m_i points (uniform over [x_0, x_{n-1}] of the curve,
+    random order).  A step is the build of every curve's y'' (a build-only
+    plan, one launch) and the evaluation of every point (one launch)."""
+    import numpy as np
+    import torch
+
+    from paper_2001_09253_amd import api, workloads
+
+    b = workloads.batch(seed=0)
+    rng = np.random.default_rng(1)
+    xq_h = np.empty(int(b.qoff[-1]))
+    for i in range(b.count):
+        x = b.x[b.koff[i]:b.koff[i + 1]]
+        xq_h[b.qoff[i]:b.qoff[i + 1]] = rng.uniform(x[0], x[-1], int(b.qoff[i + 1] - b.qoff[i]))
+    N, M = int(b.koff[-1]), int(b.qoff[-1])
+    bufs = {"x": torch.from_numpy(b.x).cuda(), "y": torch.from_numpy(b.y).cuda(),
+            "sd": torch.from_numpy(b.sd).cuda(), "ed": torch.from_numpy(b.ed).cuda(),
+            "koff": torch.from_numpy(b.koff).cuda(), "ypp": torch.empty(N, dtype=torch.float64, device="cuda")}
+    qoff = torch.from_numpy(b.qoff).cuda()
+    plan = api.spline_plan_create(b.koff, None)
+    cache = os.path.join(ROOT, "paper_2001_09253_amd", "autotune.json")
+    best, _ = api.spline_plan_autotune(plan, bufs, reps=5, cache_path=cache)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    K = args.steps
+    # points and results rotated over >= 2 GiB each, so that no step finds
+    # them in the 256 MB last-level cache
+    nrot = max(2, -(-(2 << 30) // (8 * M)))
+    xq_h_t = torch.from_numpy(xq_h)
+    rot = [{"xq": xq_h_t.cuda(), "yq": torch.empty(M, dtype=torch.float64, device="cuda"),
+            "ypp": torch.empty(N, dtype=torch.float64, device="cuda")} for _ in range(nrot)]
+    d1 = torch.empty(M, dtype=torch.float64, device="cuda")
+    d2 = torch.empty_like(d1)
+    it = [0]
+
+    def build(r):
+        api.spline_plan_run(plan, dict(bufs, ypp=r["ypp"]), stream=sp)
+
+    def points(r, derivs=False):
+        api.spline_batch_eval_points(bufs["koff"], qoff, bufs["x"], bufs["y"], r["ypp"], r["xq"], r["yq"],
+                                     d1 if derivs else None, d2 if derivs else None, stream=sp)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(K):
+            fn()
+        e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1) / K, (time.perf_counter() - t0) / K
+
+    def rotated(fn):
+        def step():
+            fn(rot[it[0] % nrot])
+            it[0] += 1
+        return step
+
+    build_ms, _ = timed(rotated(build))
+    pts_ms, _ = timed(rotated(points))
+    pts_d_ms, _ = timed(rotated(lambda r: points(r, True)))
+    step_ms, step_s = timed(rotated(lambda r: (build(r), points(r))))
+    # algorithmic bytes of the points launch: read the points and write the
+    # values (16 per query), read x, y and y'' (24 per knot), and per curve
+    # its two offsets (16); of the whole step, the build's 24 per knot more
+    dbytes = 16.0 * M + 24.0 * N + 16.0 * b.count
+    step_bytes = dbytes + 24.0 * N + 16.0 * b.count
+    achieved = dbytes / (pts_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": (N + M) / step_s, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched_points: 4096 curves, sizes log-uniform 0.1x..10x of (13 knots, 2048 "
+                               "points), explicit points U(x_0, x_{n-1}) per curve in random order; a build-only "
+                               "plan then one spline_batch_eval_points launch (values), points and outputs rotated "
+                               "over %.1f GB" % (nrot * 8 * M / 1e9),
+                   "instances": b.count, "sum_n": N, "sum_m": M, "ends": "natural/flat/twist cycle", "seed": 0,
+                   "points": "numpy default_rng(1)",
+                   "build_tuning": {"block": best.block, "queries_per_tile": best.queries_per_tile,
+                                    "grid_per_cu": best.grid_per_cu, "fused": best.fused}},
+        "roofline": {"bound": "hbm", "kernel": "eval_points_batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("eval_points_batch", "batched_points"),
+                     "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": pts_ms},
+        "kernels_ms": {"build_only_plan": build_ms, "eval_points_batch_values": pts_ms,
+                       "eval_points_batch_with_derivatives": pts_d_ms, "step_event_ms": step_ms},
+        "step_frac": step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "with_derivatives": {"ms": pts_d_ms,
+                             "frac": (dbytes + 16.0 * M) / (pts_d_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle over the whole batch, curve by curve (y'' by banded
+        # elimination, then every point bracketed and evaluated), single
+        # thread, repeated for about --cpu-seconds
+        reps = 0
+        t0 = oracle.now()
+        while True:
+            for i in range(b.count):
+                k0, k1, q0, q1 = b.koff[i], b.koff[i + 1], b.qoff[i], b.qoff[i + 1]
+                o_ypp = oracle.second_derivatives(b.x[k0:k1], b.y[k0:k1], b.sd[i], b.ed[i])
+                oracle.eval_points(b.x[k0:k1], b.y[k0:k1], o_ypp, xq_h[q0:q1])
+            reps += 1
+            if oracle.now() - t0 >= args.cpu_seconds:
+                break
+        t = oracle.now() - t0
+        out["cpu_baseline"] = {"value": (N + M) * reps / t, "unit": UNIT, "cores": 1, "kind": "oracle",
+                               "sample": "the whole batch (all %d curves: build and every point), %d repetitions "
+                                         "in %.1f s, single thread" % (b.count, reps, t),
+                               "ns_per_point": t / (M * reps) * 1e9}
+    return out
+
+
 def plain_context(args):
     """The single-curve configurations beside the batch: C2 (13,000 knots,
     2,048,000 queries) in one launch, and the same curve at m = 2^27 (out of
@@ -758,8 +881,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batched",
-                    choices=["plain", "small", "plain2x", "points", "long", "batched", "mixed", "served", "copy",
-                             "sweep"])
+                    choices=["plain", "small", "plain2x", "points", "batched_points", "long", "batched", "mixed",
+                             "served", "copy", "sweep"])
     ap.add_argument("--sorted", action="store_true", help="points: sorted query points")
     ap.add_argument("--variant", default=None,
                     choices=["newint", "newint__orig", "newint__noinv", "splint_one__div", "splint_one__mul", "horner"],
@@ -789,6 +912,8 @@ def main():
         out = bench_single(args, 13000, 1 << 27, "plain2x: 1 curve, n=13000, m=2^27 uniform queries")
     elif args.workload == "points":
         out = bench_points(args, args.sorted)
+    elif args.workload == "batched_points":
+        out = bench_batched_points(args)
     elif args.workload == "long":
         out = bench_single(args, 1 << 28, 1 << 28, "long: 1 curve, n=m=2^28 (the size sweep's largest point)",
                            cpu_sample=1 << 22)

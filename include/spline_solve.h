@@ -276,6 +276,25 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
                        const double *xq, int64_t m, double *yq, double *d1, double *d2,
                        int32_t *idx, void *stream);
 
+/* Explicit queries over a batch, in one launch (the evaluation of "Fast
+ * Interpolation" at any points, for many curves): count curves in CSR layout
+ * on the device, koff and qoff (count + 1 int64 each, non-decreasing).  Curve
+ * i owns knots koff[i] .. koff[i+1]-1 of x, y and ypp (its second
+ * derivatives: from spline_plan_run, a build-only plan, or spline_build) and
+ * queries qoff[i] .. qoff[i+1]-1; query k of the offsets is read from
+ * xq[k - qoff[0]] and its results are written to yq[k - qoff[0]] (and to d1,
+ * d2, the first and second derivative, and idx, the interval within the
+ * curve, each nullable).  total_m = qoff[count] - qoff[0] (a host value: it
+ * sizes the launch).  The interval of q is clip(#{x_j < q} - 1, 0, n_i - 2),
+ * so points outside a curve's range take its end intervals and a NaN point
+ * gives NaN.  Every n_i must be >= 3 (a curve of fewer than two knots gets
+ * NaN; the sizes are not read on the host); m_i = 0 is allowed.  Asynchronous
+ * on `stream`; allocates nothing.  Errors: E_ARG (koff, qoff, x, y, ypp, xq
+ * or yq NULL), E_SIZE (count or total_m < 1), E_DEVICE. */
+int spline_batch_eval_points(int64_t count, int64_t total_m, const int64_t *koff, const int64_t *qoff,
+                             const double *x, const double *y, const double *ypp, const double *xq,
+                             double *yq, double *d1, double *d2, int32_t *idx, void *stream);
+
 /* ============================================================================
  * Batched form: many curves in CSR layout, each solved ("Generating Second
  * Derivatives") and evaluated at its own uniform queries ("Fast
@@ -323,7 +342,10 @@ typedef struct {
 /* Plan a batch from host-side sizes: count instances, knot offsets koff[count+1]
  * and query offsets qoff[count+1] (host int64, CSR: instance i owns knots
  * koff[i]..koff[i+1]-1 and outputs qoff[i]..qoff[i+1]-1).  Every n_i must be
- * in [3, SOLVE_MAX_N_BATCH] and every m_i >= 1.  precision: SOLVE_FP64 or
+ * in [3, SOLVE_MAX_N_BATCH] and every m_i >= 1.  qoff NULL plans a build only:
+ * the runs compute the second derivatives of every curve and evaluate
+ * nothing (their qoff and yq may then be NULL; spline_batch_eval_points
+ * evaluates explicit points from the y'' they leave).  precision: SOLVE_FP64 or
  * SOLVE_FP32_REFINE.  tuning: nullable (library defaults).  The plan owns a
  * device copy of its work tables; *out must be released with
  * spline_plan_destroy.  Errors: E_ARG (also an invalid tuning), E_SIZE,

@@ -166,6 +166,20 @@ def spline_eval_points(x, y, ypp, xq, yq, d1=None, d2=None, idx=None, stream=Non
            "spline_eval_points")
 
 
+def spline_batch_eval_points(koff, qoff, x, y, ypp, xq, yq, d1=None, d2=None, idx=None, stream=None):
+    """Explicit points of many curves in one launch: koff, qoff device int64
+    (count + 1, CSR), x, y, ypp per knot, xq and yq (and d1, d2, idx) per
+    query, as many as xq holds."""
+    count = koff.numel() - 1
+    m = xq.numel()
+    _check(_native.lib().spline_batch_eval_points(
+        count, m, _dev(koff, torch.int64, "koff"), _dev(qoff, torch.int64, "qoff", count + 1), _dev(x, name="x"),
+        _dev(y, name="y", numel=x.numel()), _dev(ypp, name="ypp", numel=x.numel()), _dev(xq, name="xq"),
+        _dev(yq, name="yq", numel=m), _dev(d1, name="d1", numel=m, optional=True),
+        _dev(d2, name="d2", numel=m, optional=True), _dev(idx, torch.int32, "idx", m, optional=True),
+        _stream(stream)), "spline_batch_eval_points")
+
+
 # -- batched plans --------------------------------------------------------------------------
 
 class Plan:
@@ -187,24 +201,29 @@ class Plan:
 
 
 def spline_plan_create(koff, qoff, precision=FP64, tuning=None, device=None):
+    """qoff None: a build-only plan (y'' of every curve, no queries)."""
     koff = np.ascontiguousarray(koff, dtype=np.int64)
-    qoff = np.ascontiguousarray(qoff, dtype=np.int64)
+    qoff = None if qoff is None else np.ascontiguousarray(qoff, dtype=np.int64)
     count = len(koff) - 1
     dev = torch.cuda.current_device() if device is None else int(device)
     h = C.c_void_p()
     t = C.byref(tuning) if tuning is not None else None
     _check(_native.lib().spline_plan_create(dev, count, koff.ctypes.data_as(C.c_void_p),
-                                            qoff.ctypes.data_as(C.c_void_p), int(precision), t, C.byref(h)),
+                                            None if qoff is None else qoff.ctypes.data_as(C.c_void_p),
+                                            int(precision), t, C.byref(h)),
            "spline_plan_create")
     return Plan(h, count, koff, qoff)
 
 
 def _plan_args(plan, b):
-    n_tot, m_tot = int(plan.koff[-1]), int(plan.qoff[-1])
+    n_tot = int(plan.koff[-1])
+    build_only = plan.qoff is None
+    m_tot = 0 if build_only else int(plan.qoff[-1])
     return [_dev(b["x"], name="x", numel=n_tot), _dev(b["y"], name="y", numel=n_tot),
             _dev(b["sd"], name="sd", numel=plan.count), _dev(b["ed"], name="ed", numel=plan.count),
-            _dev(b["koff"], torch.int64, "koff", plan.count + 1), _dev(b["qoff"], torch.int64, "qoff", plan.count + 1),
-            _dev(b["yq"], name="yq", numel=m_tot), _dev(b["ypp"], name="ypp", numel=n_tot)]
+            _dev(b["koff"], torch.int64, "koff", plan.count + 1),
+            _dev(b.get("qoff"), torch.int64, "qoff", plan.count + 1, optional=build_only),
+            _dev(b.get("yq"), name="yq", numel=m_tot, optional=build_only), _dev(b["ypp"], name="ypp", numel=n_tot)]
 
 
 def spline_plan_run(plan, bufs, status=None, stream=None):

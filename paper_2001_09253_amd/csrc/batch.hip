@@ -1177,7 +1177,9 @@ int Batch::launch(const double* x, const double* y, const double* sd, const doub
 int Batch::launch_with_tables(const void* tables, const double* x, const double* y, const double* sd,
                               const double* ed, const int64_t* koff, const int64_t* qoff, double* yq, double* ypp,
                               int32_t* status, hipStream_t s, int32_t* idx, int32_t* bad) {
-    if (!tables || !x || !y || !sd || !ed || !koff || !qoff || !yq || !ypp) return SOLVE_E_ARG;
+    if (!tables || !x || !y || !sd || !ed || !koff || !ypp) return SOLVE_E_ARG;
+    // (a plan with no queries never reads qoff or writes yq)
+    if (total_m_ > 0 && (!qoff || !yq)) return SOLVE_E_ARG;
     BatchDevArgs a;
     a.x = x;
     a.y = y;
@@ -1285,8 +1287,9 @@ std::string size_class(const Batch& b) {
     const double mn = (double)b.total_n() / (double)b.count();
     const double mm = (double)b.total_m() / (double)b.count();
     char buf[128];
+    // (a build-only plan has no queries: class m-1)
     snprintf(buf, sizeof buf, "c%d_n%d_m%d_p%u", (int)std::lround(std::log2((double)b.count())),
-             (int)std::lround(std::log2(mn)), (int)std::lround(std::log2(mm)), b.precision());
+             (int)std::lround(std::log2(mn)), mm > 0.0 ? (int)std::lround(std::log2(mm)) : -1, b.precision());
     return buf;
 }
 
@@ -1338,14 +1341,24 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
 
 extern "C" int spline_plan_create(int device, int64_t count, const int64_t* koff, const int64_t* qoff,
                                   uint32_t precision, const spline_tuning* tuning, spline_plan** out) {
-    if (!out || !koff || !qoff) return SOLVE_E_ARG;
+    if (!out || !koff) return SOLVE_E_ARG;
     *out = nullptr;
+    if (count < 1) return SOLVE_E_ARG;
+    if (count > 0x7fffffffLL) return SOLVE_E_SIZE;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SOLVE_E_DEVICE;
     DeviceGuard g(device);
     spline_plan* p = new spline_plan(device);
     const spline_tuning t = tuning ? *tuning : default_tuning();
-    int rc = p->batch.plan(count, koff, qoff, t, precision);
+    int rc;
+    if (qoff) {
+        rc = p->batch.plan(count, koff, qoff, t, precision);
+    } else {
+        // build only: every curve's y'', no queries
+        const std::vector<int64_t> none((size_t)count + 1, 0);
+        const std::vector<uint8_t> no_queries((size_t)count, 0);
+        rc = p->batch.plan(count, koff, none.data(), t, precision, no_queries.data());
+    }
     if (!rc) rc = p->batch.upload(nullptr);
     if (!rc && hipStreamSynchronize(nullptr) != hipSuccess) rc = SOLVE_E_DEVICE;
     if (rc) {

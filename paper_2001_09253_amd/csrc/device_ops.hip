@@ -223,6 +223,197 @@ int launch_eval_points(const double* x, const double* y, const double* ypp, int6
     return launch_points_t<false, false>(x, y, ypp, n, xq, m, yq, nullptr, nullptr, nullptr, s);
 }
 
+// ---------------------------------------------------------------------------
+// Explicit queries over a batch of curves in CSR layout, in one launch (query
+// k of the launch is query qoff[0] + k of the offsets, read from xq[k] and
+// written to yq[k]).  The queries are stored curve after curve, so a tile of BLOCK * QPT consecutive
+// queries covers consecutive curves c0 .. c1, whose knots are consecutive
+// too.  The tile finds c0 and c1 (a 64-way search of the query offsets by one
+// wavefront each), stages the knots, values and y'' of as many of those
+// curves as fit the window, and every query then finds its curve (a search
+// of the staged query offsets) and its interval (a search of that curve's
+// staged knots) in the LDS; a curve longer than the window is searched in
+// global memory.
+// ---------------------------------------------------------------------------
+constexpr int kBatchPtsBlock = 256;
+constexpr int kBatchPtsQPT = 8;
+constexpr int kBatchPtsWin = 1024;    // knots staged per window
+constexpr int kBatchPtsCurves = 512;  // curves per window
+constexpr int kBatchPtsGroups = 4;    // workgroups per compute unit (32 KB of LDS each)
+
+struct BatchPtsSmem {
+    double sx[kBatchPtsWin];
+    double sy[kBatchPtsWin];
+    double sp[kBatchPtsWin];
+    int64_t kb[kBatchPtsCurves + 1];  // knots of window curve c: kb[c] .. kb[c+1] - 1, from the window's first
+    int64_t qb[kBatchPtsCurves + 1];  // queries of window curve c: qb[c] .. qb[c+1] - 1
+    int64_t c[2];                     // the tile's first and last curve
+    int32_t nw;                       // curves in the window
+};
+
+// Number of entries of the sorted a[0 .. len) that are <= v, by one
+// wavefront: 64 evenly spaced probes per round narrow the range to one gap
+// (the same rounds as wave_count_below).  Every lane returns the same value.
+__device__ __forceinline__ int64_t wave_count_le(const int64_t* __restrict__ a, int64_t len, int64_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t lo = 0;
+    while (len > 0) {
+        const int64_t step = (len + kWave - 1) / kWave;
+        const int64_t j = lo + (int64_t)lane * step;
+        const bool le = (j < lo + len) && (a[j] <= v);
+        const int c = __popcll(__ballot(le));
+        if (c == 0) break;
+        const int64_t jl = lo + (int64_t)(c - 1) * step;
+        const int64_t hi = min(lo + len, jl + step);
+        lo = jl + 1;
+        len = hi - lo;
+    }
+    return lo;
+}
+
+// First index i in [lo, lo + len) with a[i] > v (lo + len if none).
+__device__ __forceinline__ int first_above(const int64_t* a, int lo, int len, int64_t v) {
+    while (len > 0) {
+        const int half = len >> 1;
+        const bool le = a[lo + half] <= v;
+        lo = le ? lo + half + 1 : lo;
+        len = le ? len - half - 1 : half;
+    }
+    return lo;
+}
+
+template <bool DERIVS, bool IDX>
+__device__ __forceinline__ void put_point(const double* xs, const double* ys, const double* ps, int64_t nc,
+                                          double q, int64_t k, double* __restrict__ yq, double* __restrict__ d1,
+                                          double* __restrict__ d2, int32_t* __restrict__ idx) {
+    if (nc < 2) {  // no interval (the caller's sizes break the precondition n >= 3)
+        yq[k] = __builtin_nan("");
+        if constexpr (DERIVS) {
+            if (d1) d1[k] = __builtin_nan("");
+            if (d2) d2[k] = __builtin_nan("");
+        }
+        if constexpr (IDX) idx[k] = 0;
+        return;
+    }
+    // the definition: clip(#{x_j < q} - 1, 0, n - 2); a NaN query counts no knot
+    const int64_t i = clip_interval(lower_bound_idx(xs, 0, nc, q), nc);
+    const double a = xs[i], b = xs[i + 1];
+    const double u = ys[i], v = ys[i + 1];
+    const double up = ps[i], vp = ps[i + 1];
+    const double inv = 1.0 / (b - a);
+    yq[k] = newint(q, a, b, u, v, up, vp, inv);
+    if constexpr (DERIVS) {
+        double g1, g2;
+        newint_derivs(q, a, b, u, v, up, vp, inv, &g1, &g2);
+        if (d1) d1[k] = g1;
+        if (d2) d2[k] = g2;
+    }
+    if constexpr (IDX) idx[k] = (int32_t)i;
+}
+
+template <bool DERIVS, bool IDX>
+__global__ __launch_bounds__(kBatchPtsBlock) void eval_points_batch_kernel(
+    int64_t count, int64_t total_m, const int64_t* __restrict__ koff, const int64_t* __restrict__ qoff,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ ypp,
+    const double* __restrict__ xq, double* __restrict__ yq, double* __restrict__ d1, double* __restrict__ d2,
+    int32_t* __restrict__ idx) {
+    __shared__ BatchPtsSmem sm;
+    constexpr int B = kBatchPtsBlock;
+    constexpr int QPT = kBatchPtsQPT;
+    constexpr int64_t Q = (int64_t)B * QPT;
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    // query k of the launch is query qbase + k of the offsets
+    const int64_t qbase = qoff[0];
+    for (int64_t q0 = (int64_t)blockIdx.x * Q; q0 < total_m; q0 += (int64_t)gridDim.x * Q) {
+        const int64_t q1 = min(total_m, q0 + Q);
+        __syncthreads();  // (the previous tile is done with the LDS)
+        if (wid < 2) {
+            // the curve of the tile's first (wavefront 0) and last (1) query:
+            // the last curve whose first query is not past it
+            const int64_t v = qbase + (wid == 0 ? q0 : q1 - 1);
+            const int64_t c = max((int64_t)0, wave_count_le(qoff, count, v) - 1);
+            if ((tid & (kWave - 1)) == 0) sm.c[wid] = c;
+        }
+        __syncthreads();
+        const int64_t c0 = sm.c[0];
+        const int64_t c1 = max(sm.c[1], c0);
+        for (int64_t ca = c0; ca <= c1;) {
+            // window: curves ca .. ca + nw - 1, as many as fit (at least one)
+            const int ncand = (int)(min(c1, ca + kBatchPtsCurves - 1) - ca + 1);
+            const int64_t kbase = koff[ca];
+            for (int c = tid; c <= ncand; c += B) {
+                sm.kb[c] = koff[ca + c] - kbase;
+                sm.qb[c] = qoff[ca + c];
+            }
+            __syncthreads();
+            if (tid == 0) sm.nw = max(1, first_above(sm.kb, 1, ncand, kBatchPtsWin) - 1);
+            __syncthreads();
+            const int nw = sm.nw;
+            const int64_t nk = sm.kb[nw];
+            const bool staged = nk <= kBatchPtsWin;  // else one curve longer than the window
+            if (staged) {
+                for (int j = tid; j < nk; j += B) {
+                    sm.sx[j] = x[kbase + j];
+                    sm.sy[j] = y[kbase + j];
+                    sm.sp[j] = ypp[kbase + j];
+                }
+                __syncthreads();
+            }
+            // this thread's queries of the window: k = q0 + r B + tid in [qa, qe),
+            // each point loaded one query ahead (a loop that is not unrolled
+            // keeps the register count low enough for 16 wavefronts a CU)
+            const int64_t qa = max(q0, sm.qb[0] - qbase);
+            const int64_t qe = min(q1, sm.qb[nw] - qbase);
+            const int64_t ra = qa - q0 - tid <= 0 ? 0 : (qa - q0 - tid + B - 1) / B;
+            int64_t k = q0 + ra * B + tid;
+            double qn = k < qe ? xq[k] : 0.0;
+#pragma unroll 1
+            for (; k < qe; k += B) {
+                const double qv = qn;
+                if (k + B < qe) qn = xq[k + B];
+                // its curve: the last window curve whose first query is not past k
+                const int c = first_above(sm.qb, 1, nw - 1, qbase + k) - 1;
+                const int64_t b0 = sm.kb[c];
+                const int64_t nc = sm.kb[c + 1] - b0;
+                if (staged)
+                    put_point<DERIVS, IDX>(sm.sx + b0, sm.sy + b0, sm.sp + b0, nc, qv, k, yq, d1, d2, idx);
+                else
+                    put_point<DERIVS, IDX>(x + kbase, y + kbase, ypp + kbase, nc, qv, k, yq, d1, d2, idx);
+            }
+            __syncthreads();  // (before the next window is staged)
+            ca += nw;
+        }
+    }
+}
+
+template <bool DERIVS, bool IDX>
+static int launch_points_batch_t(int64_t count, int64_t total_m, const int64_t* koff, const int64_t* qoff,
+                                 const double* x, const double* y, const double* ypp, const double* xq, double* yq,
+                                 double* d1, double* d2, int32_t* idx, hipStream_t s) {
+    constexpr int64_t Q = (int64_t)kBatchPtsBlock * kBatchPtsQPT;
+    const int64_t tiles = (total_m + Q - 1) / Q;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * kBatchPtsGroups));
+    eval_points_batch_kernel<DERIVS, IDX><<<(unsigned)grid, kBatchPtsBlock, 0, s>>>(count, total_m, koff, qoff, x, y,
+                                                                                    ypp, xq, yq, d1, d2, idx);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
+int launch_eval_points_batch(int64_t count, int64_t total_m, const int64_t* koff, const int64_t* qoff,
+                             const double* x, const double* y, const double* ypp, const double* xq, double* yq,
+                             double* d1, double* d2, int32_t* idx, hipStream_t s) {
+    const bool derivs = d1 || d2;
+    if (derivs && idx)
+        return launch_points_batch_t<true, true>(count, total_m, koff, qoff, x, y, ypp, xq, yq, d1, d2, idx, s);
+    if (derivs)
+        return launch_points_batch_t<true, false>(count, total_m, koff, qoff, x, y, ypp, xq, yq, d1, d2, nullptr, s);
+    if (idx)
+        return launch_points_batch_t<false, true>(count, total_m, koff, qoff, x, y, ypp, xq, yq, nullptr, nullptr,
+                                                  idx, s);
+    return launch_points_batch_t<false, false>(count, total_m, koff, qoff, x, y, ypp, xq, yq, nullptr, nullptr,
+                                               nullptr, s);
+}
+
 }  // namespace spl
 
 using namespace spl;
@@ -259,4 +450,12 @@ extern "C" int spline_eval_points(const double* x, const double* y, const double
     if (!x || !y || !ypp || !xq || !yq) return SOLVE_E_ARG;
     if (n < 3 || m < 1) return SOLVE_E_SIZE;
     return launch_eval_points(x, y, ypp, n, xq, m, yq, d1, d2, idx, (hipStream_t)stream);
+}
+
+extern "C" int spline_batch_eval_points(int64_t count, int64_t total_m, const int64_t* koff, const int64_t* qoff,
+                                        const double* x, const double* y, const double* ypp, const double* xq,
+                                        double* yq, double* d1, double* d2, int32_t* idx, void* stream) {
+    if (!koff || !qoff || !x || !y || !ypp || !xq || !yq) return SOLVE_E_ARG;
+    if (count < 1 || total_m < 1) return SOLVE_E_SIZE;
+    return launch_eval_points_batch(count, total_m, koff, qoff, x, y, ypp, xq, yq, d1, d2, idx, (hipStream_t)stream);
 }

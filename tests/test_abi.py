@@ -72,6 +72,10 @@ def test_argument_errors_need_no_device(lib):
     assert lib.spline_bracket_uniform(p, 2, 5, p, None) == api.E_SIZE
     assert lib.spline_noop_uniform(None, 5, 5, p, None) == api.E_ARG
     assert lib.spline_eval_points(p, p, p, 10, None, 5, p, None, None, None, None) == api.E_ARG
+    assert lib.spline_batch_eval_points(5, 10, None, p, p, p, p, p, p, None, None, None, None) == api.E_ARG
+    assert lib.spline_batch_eval_points(5, 10, p, p, p, p, p, p, None, None, None, None, None) == api.E_ARG
+    assert lib.spline_batch_eval_points(0, 10, p, p, p, p, p, p, p, None, None, None, None) == api.E_SIZE
+    assert lib.spline_batch_eval_points(5, 0, p, p, p, p, p, p, p, None, None, None, None) == api.E_SIZE
     assert lib.solve_create(None, None) == api.E_ARG
     assert lib.solve_poll(None, 1, None) == api.E_ARG
     assert lib.solve_destroy(None) == api.E_ARG
