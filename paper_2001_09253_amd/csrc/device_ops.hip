@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "spline_kernels.hpp"
 #include "spline_solve.h"
@@ -232,19 +233,22 @@ int launch_eval_points(const double* x, const double* y, const double* ypp, int6
 // wavefront each), stages the knots, values and y'' of as many of those
 // curves as fit the window, and every query then finds its curve (a search
 // of the staged query offsets) and its interval (a search of that curve's
-// staged knots) in the LDS; a curve longer than the window is searched in
-// global memory.
+// staged knots) in the LDS.  A curve longer than the window stages every
+// stride-th knot as a fence instead, and its points finish the search in
+// global memory (as the single-curve kernel does).  The windows are kept
+// small: the kernel is bound by its search and evaluation instructions, and
+// smaller workgroups' LDS lets more wavefronts share a compute unit.
 // ---------------------------------------------------------------------------
 constexpr int kBatchPtsBlock = 256;
 constexpr int kBatchPtsQPT = 8;
-constexpr int kBatchPtsWin = 1024;    // knots staged per window
-constexpr int kBatchPtsCurves = 512;  // curves per window
-constexpr int kBatchPtsGroups = 4;    // workgroups per compute unit (32 KB of LDS each)
+constexpr int kBatchPtsWin = 512;     // knots staged per window
+constexpr int kBatchPtsCurves = 256;  // curves per window
 
 struct BatchPtsSmem {
     double sx[kBatchPtsWin];
     double sy[kBatchPtsWin];
     double sp[kBatchPtsWin];
+    double sw[kBatchPtsWin];  // 1 / (x_{j+1} - x_j): an interval's one division, formed once
     int64_t kb[kBatchPtsCurves + 1];  // knots of window curve c: kb[c] .. kb[c+1] - 1, from the window's first
     int64_t qb[kBatchPtsCurves + 1];  // queries of window curve c: qb[c] .. qb[c+1] - 1
     int64_t c[2];                     // the tile's first and last curve
@@ -311,6 +315,42 @@ __device__ __forceinline__ void put_point(const double* xs, const double* ys, co
     if constexpr (IDX) idx[k] = (int32_t)i;
 }
 
+// A point of a curve staged in the LDS (nc >= 2 knots at xs, reciprocal
+// widths at sw).
+template <bool DERIVS, bool IDX>
+__device__ __forceinline__ void put_point_lds(const double* xs, const double* ys, const double* ps, const double* sw,
+                                              int nc, double q, int64_t k, double* __restrict__ yq,
+                                              double* __restrict__ d1, double* __restrict__ d2,
+                                              int32_t* __restrict__ idx) {
+    if (nc < 2) {
+        put_point<DERIVS, IDX>(xs, ys, ps, nc, q, k, yq, d1, d2, idx);
+        return;
+    }
+    // #{x_j < q}: bisection that keeps the base of the remaining range and
+    // halves its length (a NaN query counts no knot)
+    int base = 0, len = nc;
+    while (len > 1) {
+        const int half = len >> 1;
+        base = xs[base + half] < q ? base + half : base;
+        len -= half;
+    }
+    const int cnt = base + (xs[base] < q ? 1 : 0);
+    // the definition: clip(#{x_j < q} - 1, 0, n - 2)
+    const int i = min(max(cnt - 1, 0), nc - 2);
+    const double a = xs[i], b = xs[i + 1];
+    const double u = ys[i], v = ys[i + 1];
+    const double up = ps[i], vp = ps[i + 1];
+    const double inv = sw[i];
+    yq[k] = newint(q, a, b, u, v, up, vp, inv);
+    if constexpr (DERIVS) {
+        double g1, g2;
+        newint_derivs(q, a, b, u, v, up, vp, inv, &g1, &g2);
+        if (d1) d1[k] = g1;
+        if (d2) d2[k] = g2;
+    }
+    if constexpr (IDX) idx[k] = i;
+}
+
 template <bool DERIVS, bool IDX>
 __global__ __launch_bounds__(kBatchPtsBlock) void eval_points_batch_kernel(
     int64_t count, int64_t total_m, const int64_t* __restrict__ koff, const int64_t* __restrict__ qoff,
@@ -352,17 +392,30 @@ __global__ __launch_bounds__(kBatchPtsBlock) void eval_points_batch_kernel(
             const int nw = sm.nw;
             const int64_t nk = sm.kb[nw];
             const bool staged = nk <= kBatchPtsWin;  // else one curve longer than the window
+            int64_t stride = 1;
+            int nf = 0;
             if (staged) {
                 for (int j = tid; j < nk; j += B) {
-                    sm.sx[j] = x[kbase + j];
+                    const double xj = x[kbase + j];
+                    sm.sx[j] = xj;
                     sm.sy[j] = y[kbase + j];
                     sm.sp[j] = ypp[kbase + j];
+                    // (across a curve boundary the entry is never read)
+                    if (j + 1 < nk) sm.sw[j] = 1.0 / (x[kbase + j + 1] - xj);
                 }
-                __syncthreads();
+            } else {
+                // a curve longer than the window: every stride-th knot staged
+                // as a fence, the search finished in global memory
+                stride = (nk + kBatchPtsWin - 1) / kBatchPtsWin;
+                nf = (int)((nk + stride - 1) / stride);
+                for (int f = tid; f < nf; f += B) sm.sx[f] = x[kbase + (int64_t)f * stride];
             }
+            __syncthreads();
             // this thread's queries of the window: k = q0 + r B + tid in [qa, qe),
             // each point loaded one query ahead (a loop that is not unrolled
-            // keeps the register count low enough for 16 wavefronts a CU)
+            // keeps the register count low: the kernel is bound by its search
+            // and evaluation instructions and gains from every resident
+            // wavefront)
             const int64_t qa = max(q0, sm.qb[0] - qbase);
             const int64_t qe = min(q1, sm.qb[nw] - qbase);
             const int64_t ra = qa - q0 - tid <= 0 ? 0 : (qa - q0 - tid + B - 1) / B;
@@ -377,9 +430,11 @@ __global__ __launch_bounds__(kBatchPtsBlock) void eval_points_batch_kernel(
                 const int64_t b0 = sm.kb[c];
                 const int64_t nc = sm.kb[c + 1] - b0;
                 if (staged)
-                    put_point<DERIVS, IDX>(sm.sx + b0, sm.sy + b0, sm.sp + b0, nc, qv, k, yq, d1, d2, idx);
+                    put_point_lds<DERIVS, IDX>(sm.sx + b0, sm.sy + b0, sm.sp + b0, sm.sw + b0, (int)nc, qv, k, yq, d1,
+                                               d2, idx);
                 else
-                    put_point<DERIVS, IDX>(x + kbase, y + kbase, ypp + kbase, nc, qv, k, yq, d1, d2, idx);
+                    eval_point<DERIVS, IDX>(x + kbase, y + kbase, ypp + kbase, nc, sm.sx, nf, stride, qv, k, yq, d1,
+                                            d2, idx);
             }
             __syncthreads();  // (before the next window is staged)
             ca += nw;
@@ -391,9 +446,23 @@ template <bool DERIVS, bool IDX>
 static int launch_points_batch_t(int64_t count, int64_t total_m, const int64_t* koff, const int64_t* qoff,
                                  const double* x, const double* y, const double* ypp, const double* xq, double* yq,
                                  double* d1, double* d2, int32_t* idx, hipStream_t s) {
+    // one round of the workgroups the device holds at once (looked up once
+    // per device; relaxed atomics: two host threads may both look it up and
+    // store the same value)
+    static std::atomic<int> per_cu[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int v = per_cu[dev].load(std::memory_order_relaxed);
+    if (!v) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, eval_points_batch_kernel<DERIVS, IDX>, kBatchPtsBlock,
+                                                         0) != hipSuccess ||
+            v <= 0)
+            v = 1;
+        per_cu[dev].store(v, std::memory_order_relaxed);
+    }
     constexpr int64_t Q = (int64_t)kBatchPtsBlock * kBatchPtsQPT;
     const int64_t tiles = (total_m + Q - 1) / Q;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * kBatchPtsGroups));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * v));
     eval_points_batch_kernel<DERIVS, IDX><<<(unsigned)grid, kBatchPtsBlock, 0, s>>>(count, total_m, koff, qoff, x, y,
                                                                                     ypp, xq, yq, d1, d2, idx);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;

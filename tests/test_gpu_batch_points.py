@@ -138,20 +138,20 @@ def test_batch_points_values_only_equal_single_curve_kernel():
 @pytest.mark.parametrize("case", ["tiny_m", "empty", "long_curves", "window_split", "ragged"])
 def test_batch_points_tile_edges(case):
     """Tiles across many curves (more than one window of curves), curves with
-    no points, curves longer than the staged window (searched in global
-    memory), tiles whose curves' knots need several windows, and a total that
-    is no multiple of the tile."""
+    no points, curves longer than the staged window (a fence table in the LDS,
+    the search finished in global memory), tiles whose curves' knots need
+    several windows, and a total that is no multiple of the tile."""
     rng = np.random.default_rng(["tiny_m", "empty", "long_curves", "window_split", "ragged"].index(case) + 30)
-    if case == "tiny_m":       # 3000 curves of 1-3 points: tiles span > 512 curves
+    if case == "tiny_m":       # 3000 curves of 1-3 points: tiles span > 256 curves
         n = rng.integers(3, 40, 3000)
         m = rng.integers(1, 4, 3000)
     elif case == "empty":      # every other curve without points
         n = rng.integers(3, 130, 400)
         m = np.where(np.arange(400) % 2 == 0, 0, rng.integers(1, 600, 400))
-    elif case == "long_curves":  # 2048-knot curves (longer than the 1024-knot window)
+    elif case == "long_curves":  # 2048-knot curves (longer than the 512-knot window: fenced search)
         n = np.array([2048, 5, 2048, 1500, 3, 2048])
         m = np.array([5000, 7, 3000, 4100, 1, 2100])
-    elif case == "window_split":  # several 300-900-knot curves in one tile
+    elif case == "window_split":  # 300-900-knot curves: several windows a tile, some fenced
         n = rng.integers(300, 900, 60)
         m = rng.integers(20, 200, 60)
     else:
