@@ -336,6 +336,9 @@ int size_slot(solve_ctx* c, Slot& s) {
 // Stage, copy and launch one batch on slot s (called without the lock; the
 // slot is owned by the scheduler thread until its event completes).
 int launch_batch(solve_ctx* c, Slot& s) {
+    // requests with explicit points last, so that their points and results
+    // are contiguous and one launch evaluates them all
+    std::stable_partition(s.reqs.begin(), s.reqs.end(), [](const ReqP& r) { return !r->explicit_q(); });
     const int64_t count = (int64_t)s.reqs.size();
     int64_t nt = 0, mt = 0, xt = 0;
     bool host_yq = false, host_ypp = false;
@@ -425,14 +428,14 @@ int launch_batch(solve_ctx* c, Slot& s) {
         rc = spl::launch_solve_uniform(dx + s.koff[i], dy + s.koff[i], r.n, r.sd, r.ed, r.explicit_q() ? 1 : r.m,
                                        dyq + s.qoff[i], dypp + s.koff[i], nullptr, nullptr, st);
     }
-    xo = 0;
-    for (int64_t i = 0; i < count && !rc; ++i) {
-        const Req& r = *s.reqs[i];
-        if (!r.explicit_q()) continue;
-        rc = spl::launch_eval_points(dx + s.koff[i], dy + s.koff[i], dypp + s.koff[i], r.n,
-                                     s.din_at<double>(s.o_xq) + xo, r.m, dyq + s.qoff[i], nullptr, nullptr, nullptr,
-                                     st);
-        xo += r.m;
+    // every request with explicit points (the last count - e0 of the batch)
+    // in one launch, from the y'' the kernels above left
+    if (!rc && xt > 0) {
+        const int64_t e0 = count - (int64_t)std::count_if(s.reqs.begin(), s.reqs.end(),
+                                                          [](const ReqP& r) { return r->explicit_q(); });
+        rc = spl::launch_eval_points_batch(count - e0, xt, s.din_at<int64_t>(s.o_koff) + e0,
+                                           s.din_at<int64_t>(s.o_qoff) + e0, dx, dy, dypp, s.din_at<double>(s.o_xq),
+                                           dyq + s.qoff[e0], nullptr, nullptr, nullptr, st);
     }
     // Results: device-resident callers get a device-to-device copy; host
     // callers are served from one copy of the output region.
