@@ -173,10 +173,12 @@ __global__ __launch_bounds__(kWave) void mixed_build_kernel(BatchDevArgs a) {
 
 // ---------------------------------------------------------------------------
 // Phase 1 in mixed precision, lane-parallel, for the curves of at most
-// kLaneBuildMaxN knots: kGroupLanes lanes per curve (one DPP row, four curves
-// per wavefront), each lane owning up to CH consecutive rows.  The FP32 solver
-// is the paper's elimination with its three recurrences split over the lanes'
-// chunks and joined by scans inside the row:
+// kLaneBuildMaxN knots: one wavefront per curve, each lane owning up to CH
+// consecutive rows.  (Sixteen lanes per curve, four curves to a wavefront,
+// took 14.1 against 10.3 us on the 4096-curve batch: a wavefront per SIMD
+// then leaves every latency of the scans exposed.)  The FP32 solver is the
+// paper's elimination with its three recurrences split over the lanes'
+// chunks and joined by scans across the wavefront:
 //   pivots   c'_j = c_j / (b_j - a_j c'_{j-1}): a projective map of (P, Q)
 //            (c' = P/Q) per row, the matrix [[0, c], [-a, b]];
 //   forward  d'_j = (r_j - a_j d'_{j-1}) / (b_j - a_j c'_{j-1}): affine in d';
@@ -186,6 +188,8 @@ __global__ __launch_bounds__(kWave) void mixed_build_kernel(BatchDevArgs a) {
 // scan.  The rows are formed in FP64 and rounded to FP32; residuals and the
 // updates of y'' are FP64, the neighbouring lanes' y'' taken by DPP.
 // ---------------------------------------------------------------------------
+constexpr int kMixedBlock = 256;  // threads of a workgroup of the grouped build
+
 struct Mob32 {  // (P, Q) -> (m00 P + m01 Q, m10 P + m11 Q)
     float m00, m01, m10, m11;
 };
@@ -193,9 +197,10 @@ struct Aff32 {  // v -> K v + H
     float K, H;
 };
 
-template <int CTRL>
+template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ float dpp_f32(float old, float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xf, 0xf, false));
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
 // Scale by a power of two (exact) so that the largest entry lies in [0.5, 1);
@@ -224,48 +229,58 @@ __device__ __forceinline__ Aff32 aff_compose(const Aff32& O, const Aff32& I) {
     return Aff32{O.K * I.K, O.K * I.H + O.H};
 }
 
-template <int CTRL>
+template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ Mob32 dpp_mob(const Mob32& v) {
-    return Mob32{dpp_f32<CTRL>(1.0f, v.m00), dpp_f32<CTRL>(0.0f, v.m01), dpp_f32<CTRL>(0.0f, v.m10),
-                 dpp_f32<CTRL>(1.0f, v.m11)};
+    return Mob32{dpp_f32<CTRL, ROW_MASK>(1.0f, v.m00), dpp_f32<CTRL, ROW_MASK>(0.0f, v.m01),
+                 dpp_f32<CTRL, ROW_MASK>(0.0f, v.m10), dpp_f32<CTRL, ROW_MASK>(1.0f, v.m11)};
 }
-template <int CTRL>
+template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ Aff32 dpp_aff(const Aff32& v) {
-    return Aff32{dpp_f32<CTRL>(1.0f, v.K), dpp_f32<CTRL>(0.0f, v.H)};
+    return Aff32{dpp_f32<CTRL, ROW_MASK>(1.0f, v.K), dpp_f32<CTRL, ROW_MASK>(0.0f, v.H)};
 }
 
-// Exclusive scans inside each row of 16 lanes: the prefix composes the lanes
-// before (inner) with later lanes outer, the suffix the lanes after (inner);
-// a lane with nothing before (after) it gets the identity.
-__device__ __forceinline__ Mob32 row_excl_prefix_mob(Mob32 v) {
+// Exclusive scans over a wavefront: the prefix composes the lanes before
+// (inner) with later lanes outer, the suffix the lanes after (inner); a lane
+// with nothing before (after) it gets the identity.  The prefix takes DPP row
+// shifts inside each row of 16 lanes, then the row broadcasts of lanes 15 and
+// 31 and a shift by one lane; the suffix takes lane shuffles.
+__device__ __forceinline__ Mob32 wave_excl_prefix_mob(Mob32 v) {
     v = mob_compose(v, dpp_mob<kDppRowShr1>(v));
     v = mob_compose(v, dpp_mob<kDppRowShr2>(v));
     v = mob_compose(v, dpp_mob<kDppRowShr4>(v));
     v = mob_compose(v, dpp_mob<kDppRowShr8>(v));
-    return dpp_mob<kDppRowShr1>(v);
+    v = mob_compose(v, dpp_mob<kDppRowBcast15, 0xa>(v));
+    v = mob_compose(v, dpp_mob<kDppRowBcast31, 0xc>(v));
+    return dpp_mob<kDppWaveShr1>(v);
 }
-__device__ __forceinline__ Aff32 row_excl_prefix_aff(Aff32 v) {
+__device__ __forceinline__ Aff32 wave_excl_prefix_aff(Aff32 v) {
     v = aff_compose(v, dpp_aff<kDppRowShr1>(v));
     v = aff_compose(v, dpp_aff<kDppRowShr2>(v));
     v = aff_compose(v, dpp_aff<kDppRowShr4>(v));
     v = aff_compose(v, dpp_aff<kDppRowShr8>(v));
-    return dpp_aff<kDppRowShr1>(v);
+    v = aff_compose(v, dpp_aff<kDppRowBcast15, 0xa>(v));
+    v = aff_compose(v, dpp_aff<kDppRowBcast31, 0xc>(v));
+    return dpp_aff<kDppWaveShr1>(v);
 }
-__device__ __forceinline__ Aff32 row_excl_suffix_aff(Aff32 v) {
-    v = aff_compose(v, dpp_aff<kDppRowShl1>(v));
-    v = aff_compose(v, dpp_aff<kDppRowShl2>(v));
-    v = aff_compose(v, dpp_aff<kDppRowShl4>(v));
-    v = aff_compose(v, dpp_aff<kDppRowShl8>(v));
-    return dpp_aff<kDppRowShl1>(v);
+__device__ __forceinline__ Aff32 wave_excl_suffix_aff(Aff32 v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const Aff32 o{__shfl_down(v.K, d), __shfl_down(v.H, d)};
+        if (lane + d < kWave) v = aff_compose(v, o);
+    }
+    const Aff32 ex{__shfl_down(v.K, 1), __shfl_down(v.H, 1)};
+    return lane == kWave - 1 ? Aff32{1.0f, 0.0f} : ex;
 }
 
 template <int CH>
-__global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_build_kernel(BatchDevArgs a) {
-    __shared__ double lds_x[kGroupsPerBlock][kGroupLanes * CH];
-    __shared__ double lds_y[kGroupsPerBlock][kGroupLanes * CH];
-    const int grp = threadIdx.x / kGroupLanes;
-    const int gl = threadIdx.x & (kGroupLanes - 1);
-    const int64_t slot = (int64_t)blockIdx.x * kGroupsPerBlock + grp;
+__global__ __launch_bounds__(kMixedBlock) void mixed_group_build_kernel(BatchDevArgs a) {
+    constexpr int G = kWave;             // lanes per curve
+    constexpr int NG = kMixedBlock / G;  // curves per workgroup
+    __shared__ double lds_x[NG][G * CH];
+    __shared__ double lds_y[NG][G * CH];
+    const int grp = threadIdx.x / G;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t slot = (int64_t)blockIdx.x * NG + grp;
     const bool has = slot < a.n_lane;  // groups past the list run with no rows
     const int i = has ? a.lane_curves[slot] : 0;
     const int64_t ko = has ? a.koff[i] : 0;
@@ -276,13 +291,13 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
     const bool nat_e = natural_end(ed);
     double* sl = lds_x[grp];
     double* sv = lds_y[grp];
-    // rows s .. s + cnt - 1 are this lane's (n <= kGroupLanes * CH)
-    const int r = (n + kGroupLanes - 1) / kGroupLanes;
+    // rows s .. s + cnt - 1 are this lane's (n <= G * CH)
+    const int r = (n + G - 1) / G;
     const int s = gl * r;
     const int cnt = max(0, min(n, s + r) - s);
 
     // a1: knots and values staged through the LDS in one load round
-    for (int j = gl; j < n; j += kGroupLanes) {
+    for (int j = gl; j < n; j += G) {
         sl[j] = a.x[ko + j];
         sv[j] = a.y[ko + j];
     }
@@ -306,7 +321,7 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
             }
         }
     }
-    bad = group_any<true, kGroupLanes>(bad);
+    bad = group_any<true, G>(bad);
     // a1/a2: slopes and right-hand sides (FP64)
     double d[CH];
     {
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
                 wa = w[k];
             }
         }
-        const Mob32 pre = row_excl_prefix_mob(mob_normalize(acc));
+        const Mob32 pre = wave_excl_prefix_mob(mob_normalize(acc));
         float cpv = pre.m01 / pre.m11;
         wa = wprev0;
 #pragma unroll
@@ -378,7 +393,7 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
         for (int k = 0; k < CH; ++k) {
             if (k < cnt) f = Aff32{g[k] * f.K, g[k] * f.H + t[k] * rf[k]};
         }
-        float dp = row_excl_prefix_aff(f).H;
+        float dp = wave_excl_prefix_aff(f).H;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
             if (k < cnt) {
@@ -392,7 +407,7 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
         for (int k = CH - 1; k >= 0; --k) {
             if (k < cnt) bk = aff_compose(Aff32{-cp[k], t[k]}, bk);
         }
-        float yv = row_excl_suffix_aff(bk).H;
+        float yv = wave_excl_suffix_aff(bk, gl).H;
 #pragma unroll
         for (int k = CH - 1; k >= 0; --k) {
             if (k < cnt) {
@@ -413,8 +428,8 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
         for (int k = 0; k < CH; ++k) {
             if (k == cnt - 1) ylast = yh[k];
         }
-        const double yleft = dpp_f64<kDppRowShr1, 0xf>(0.0, ylast);
-        const double yright = dpp_f64<kDppRowShl1, 0xf>(0.0, yh[0]);
+        const double yleft = dpp_f64<kDppWaveShr1, 0xf>(0.0, ylast);
+        const double yright = dpp_f64<kDppWaveShl1, 0xf>(0.0, yh[0]);
         double wa = wprev0;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -443,7 +458,7 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void mixed_group_bui
         if (k < cnt) sl[s + k] = bad ? nan : yh[k];
     }
     wave_sync();
-    for (int j = gl; j < n; j += kGroupLanes) a.ypp[ko + j] = sl[j];
+    for (int j = gl; j < n; j += G) a.ypp[ko + j] = sl[j];
     if (has && gl == 0) {
         a.bad[i] = bad ? 1 : 0;
         if (a.status) a.status[i] = bad ? kStatusOrder : kStatusOk;
@@ -1169,6 +1184,24 @@ int Batch::upload(hipStream_t s) {
     return SOLVE_OK;
 }
 
+// The grouped mixed-precision build: one wavefront per curve, the fewest
+// rows per lane that hold the batch's longest curve of at most
+// kLaneBuildMaxN knots.
+template <int CH>
+static void launch_mixed_group(const BatchDevArgs& b, hipStream_t s) {
+    constexpr int NG = kMixedBlock / kWave;
+    const unsigned g = (unsigned)((b.n_lane + NG - 1) / NG);
+    mixed_group_build_kernel<CH><<<g, kMixedBlock, 0, s>>>(b);
+}
+
+static void launch_mixed_grouped(const BatchDevArgs& b, int64_t longest, hipStream_t s) {
+    static_assert(kLaneBuildMaxN <= 4 * kWave, "the widest grouped build holds 4 rows per lane");
+    if (longest <= kWave) launch_mixed_group<1>(b, s);
+    else if (longest <= 2 * kWave) launch_mixed_group<2>(b, s);
+    else if (longest <= 3 * kWave) launch_mixed_group<3>(b, s);
+    else launch_mixed_group<4>(b, s);
+}
+
 int Batch::launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
                   const int64_t* qoff, double* yq, double* ypp, int32_t* status, hipStream_t s, int32_t* idx) {
     return launch_with_tables(d_tables_, x, y, sd, ed, koff, qoff, yq, ypp, status, s, idx);
@@ -1208,14 +1241,7 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
                 BatchDevArgs b = a;
                 b.lane_curves += lane_long_;
                 b.n_lane = a.n_lane - lane_long_;
-                const unsigned g = (unsigned)((b.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);
-                const int64_t short_max = n_[lane_[lane_long_]];
-                if (short_max <= kGroupLanes * 4)
-                    mixed_group_build_kernel<4><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
-                else if (short_max <= kGroupLanes * 9)
-                    mixed_group_build_kernel<9><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
-                else
-                    mixed_group_build_kernel<16><<<g, kGroupLanes * kGroupsPerBlock, 0, s>>>(b);
+                launch_mixed_grouped(b, n_[lane_[lane_long_]], s);
             }
         } else {
             const unsigned g = (unsigned)((a.n_lane + kGroupsPerBlock - 1) / kGroupsPerBlock);

@@ -32,8 +32,9 @@ def walk(koff, qoff, precision, tuning):
     ch = rows // 64
     # the first launch builds the curves of up to LANE_BUILD_MAX knots with
     # tuning fused = 2 (16 lanes per curve), every curve in mixed precision:
-    # those past LANE_BUILD_MAX knots one wavefront each (LDS arrays of
-    # MAX_N_BATCH rows), the others 16 lanes each, as in the FP64 form
+    # those past LANE_BUILD_MAX knots one wavefront each with the sweeps on one
+    # lane (LDS arrays of MAX_N_BATCH rows), the others one wavefront each with
+    # the rows spread over its lanes (LDS arrays of 64 CH rows, CH <= 4)
     mixed = precision == api.FP32_REFINE
     prebuilt = api.MAX_N_BATCH if mixed else LANE_BUILD_MAX if t.fused == 2 else 0
     assert sorted(lane.tolist()) == [i for i in range(count) if n[i] <= prebuilt]
@@ -46,7 +47,9 @@ def walk(koff, qoff, precision, tuning):
             # slots 0 .. n_long - 1, the grouped launch the rest
             n_long = int(np.count_nonzero(n[lane] > LANE_BUILD_MAX))
             assert np.all(n[lane][:n_long] > LANE_BUILD_MAX) and np.all(n[lane][n_long:] <= LANE_BUILD_MAX)
-        if len(grouped):
+        if len(grouped) and mixed:
+            assert grouped.max() <= 64 * -(-int(grouped.max()) // 64) <= 64 * 4  # the wavefront's LDS rows
+        elif len(grouped):
             lane_ch = 4 if grouped.max() <= GROUP_LANES * 4 else 9 if grouped.max() <= GROUP_LANES * 9 else 16
             assert grouped.max() <= GROUP_LANES * lane_ch  # the group's LDS rows (16 CH + 2)
     # item fields against the offsets
