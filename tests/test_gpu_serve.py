@@ -84,6 +84,28 @@ def test_requests_match_oracle(flags):
         assert_close(yq, o_yq, "request %d yq" % r)
 
 
+@pytest.mark.parametrize("explicit", ["all", "every_third"])
+def test_explicit_points_share_one_launch(explicit):
+    """Requests with explicit points are evaluated together, one launch per
+    batch, after the batch is reordered so that they come last: every
+    request explicit, and every third (the reordering moves the others)."""
+    sizes = SIZES * 2
+    ex = set(range(len(sizes))) if explicit == "all" else set(range(0, len(sizes), 3))
+    reqs = make_reqs(30, sizes, explicit=ex)
+    ctx = api.solve_create()
+    try:
+        sts, res = run_all(ctx, reqs)
+        stats = api.solve_stats(ctx)
+    finally:
+        api.solve_destroy(ctx)
+    assert stats["completed"] == len(reqs)
+    for r, (req, st, (yq, ypp)) in enumerate(zip(reqs, sts, res)):
+        assert st == api.DONE, r
+        o_yq, o_ypp = expected(req)
+        assert_close(ypp, o_ypp, "request %d ypp" % r)
+        assert_close(yq, o_yq, "request %d yq" % r)
+
+
 def test_device_outputs_and_device_inputs():
     reqs = make_reqs(2, SIZES[:8])
     ctx = api.solve_create()
