@@ -51,8 +51,9 @@ __global__ __launch_bounds__(kGroupLanes * kGroupsPerBlock) void group_build_ker
 
 // ---------------------------------------------------------------------------
 // Phase 1 in mixed precision (SOLVE_FP32_REFINE) for the curves past
-// kLaneBuildMaxN knots: one wavefront per curve.  The rows of a1-a2 are formed in FP64 (all lanes); the paper's forward
-// elimination and back substitution run in FP32 over them (lane 0); then
+// kMixedWaveMaxN knots: one wavefront per curve.  The rows of a1-a2 are
+// formed in FP64 (all lanes); the paper's forward elimination and back
+// substitution run in FP32 over them (lane 0); then
 // REFINE times the FP64 residual d - T y'' of the same rows is formed (all
 // lanes) and the FP32 sweeps solve for its correction (lane 0), which is added
 // in FP64: iterative refinement with an FP32 solver.
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kWave) void mixed_build_kernel(BatchDevArgs a) {
 
 // ---------------------------------------------------------------------------
 // Phase 1 in mixed precision, lane-parallel, for the curves of at most
-// kLaneBuildMaxN knots: one wavefront per curve, each lane owning up to CH
+// kMixedWaveMaxN knots: one wavefront per curve, each lane owning up to CH
 // consecutive rows.  (Sixteen lanes per curve, four curves to a wavefront,
 // took 14.1 against 10.3 us on the 4096-curve batch: a wavefront per SIMD
 // then leaves every latency of the scans exposed.)  The FP32 solver is the
@@ -1050,7 +1051,7 @@ void Batch::make_tables() {
     }
     std::stable_sort(lane_.begin(), lane_.end(), [&](int32_t p, int32_t q) { return n_[p] > n_[q]; });
     lane_long_ = 0;
-    while (lane_long_ < (int64_t)lane_.size() && n_[lane_[lane_long_]] > kLaneBuildMaxN) ++lane_long_;
+    while (lane_long_ < (int64_t)lane_.size() && n_[lane_[lane_long_]] > kMixedWaveMaxN) ++lane_long_;
     // phase 2: whole curves when they fit one wavefront's rows, else knot
     // blocks (with halos when the item solves its own span); shares of at
     // most about queries_per_tile queries
@@ -1184,9 +1185,9 @@ int Batch::upload(hipStream_t s) {
     return SOLVE_OK;
 }
 
-// The grouped mixed-precision build: one wavefront per curve, the fewest
-// rows per lane that hold the batch's longest curve of at most
-// kLaneBuildMaxN knots.
+// The lane-parallel mixed-precision build: one wavefront per curve, the
+// fewest rows per lane (of those compiled) that hold the batch's longest
+// curve of at most kMixedWaveMaxN knots.
 template <int CH>
 static void launch_mixed_group(const BatchDevArgs& b, hipStream_t s) {
     constexpr int NG = kMixedBlock / kWave;
@@ -1195,11 +1196,13 @@ static void launch_mixed_group(const BatchDevArgs& b, hipStream_t s) {
 }
 
 static void launch_mixed_grouped(const BatchDevArgs& b, int64_t longest, hipStream_t s) {
-    static_assert(kLaneBuildMaxN <= 4 * kWave, "the widest grouped build holds 4 rows per lane");
+    static_assert(kMixedWaveMaxN <= 8 * kWave, "the widest lane-parallel build holds 8 rows per lane");
     if (longest <= kWave) launch_mixed_group<1>(b, s);
     else if (longest <= 2 * kWave) launch_mixed_group<2>(b, s);
     else if (longest <= 3 * kWave) launch_mixed_group<3>(b, s);
-    else launch_mixed_group<4>(b, s);
+    else if (longest <= 4 * kWave) launch_mixed_group<4>(b, s);
+    else if (longest <= 6 * kWave) launch_mixed_group<6>(b, s);
+    else launch_mixed_group<8>(b, s);
 }
 
 int Batch::launch(const double* x, const double* y, const double* sd, const double* ed, const int64_t* koff,
@@ -1234,8 +1237,8 @@ int Batch::launch_with_tables(const void* tables, const double* x, const double*
     if (a.n_lane > 0) {
         if (!a.bad) return SOLVE_E_ARG;
         if (mixed) {
-            // the curves past kLaneBuildMaxN knots (first in the list): one
-            // wavefront each; the others kGroupLanes lanes each
+            // the curves past kMixedWaveMaxN knots (first in the list): the
+            // one-lane sweeps; the others the lane-parallel build
             if (lane_long_ > 0) mixed_build_kernel<SOLVE_MAX_N_BATCH><<<(unsigned)lane_long_, kWave, 0, s>>>(a);
             if (a.n_lane > lane_long_) {
                 BatchDevArgs b = a;

@@ -26,6 +26,7 @@ namespace spl {
 
 constexpr uint8_t kCurveSkip = 2;    // Batch::plan: a curve the batch's kernels leave alone
 constexpr int kLaneBuildMaxN = 256;  // curves up to this many knots are built in phase 1
+constexpr int kMixedWaveMaxN = 512;  // mixed precision: curves up to this many knots take the lane-parallel build
 constexpr int kBatchHalo = 128;      // halo rows on either side of a knot block
 constexpr int kWaveMaxCH = 8;        // rows per lane of the largest wave span
 constexpr int kWaveSpanMax = 64 * kWaveMaxCH;
@@ -129,7 +130,7 @@ private:
     std::vector<WaveItem> witems_;
     std::vector<int32_t> lane_;
     int64_t lane_max_n_ = 0;
-    int64_t lane_long_ = 0;  // leading lane_ entries past kLaneBuildMaxN knots
+    int64_t lane_long_ = 0;  // leading lane_ entries past kMixedWaveMaxN knots (mixed precision)
     int64_t prebuilt_max_n_ = 0;
     void* d_bad_ = nullptr;
     size_t cap_bad_ = 0;

@@ -263,13 +263,13 @@ def test_mixed_precision_within_stated_error(small_batch, small_batch_oracle, tu
     assert e_yq.max() > 1e-12
 
 
-@pytest.mark.parametrize("top", [3, 64, 65, 128, 129, 192, 193, 256, 257])
+@pytest.mark.parametrize("top", [3, 64, 65, 128, 129, 192, 193, 256, 257, 384, 385, 512, 513])
 def test_mixed_precision_each_group_width(top):
-    """The lane-parallel FP32 build at each of its widths (1 to 4 rows per
-    lane of a wavefront, chosen by the batch's longest curve of at most 256
-    knots), every end condition, curves from 3 knots up to the top size; with
-    top = 257 one curve goes to the one-lane sweep build and the rest to the
-    lane-parallel one."""
+    """The lane-parallel FP32 build at each of its widths (1, 2, 3, 4, 6 or 8
+    rows per lane of a wavefront, chosen by the batch's longest curve of at
+    most 512 knots), every end condition, curves from 3 knots up to the top
+    size; with top = 513 one curve goes to the one-lane sweep build and the
+    rest to the lane-parallel one."""
     rng = np.random.default_rng(top)
     n = np.concatenate([[3, 4, 5, top, top], rng.integers(3, top + 1, 59)]).astype(np.int64)
     m = rng.integers(1, 3000, len(n)).astype(np.int64)

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 HALO = 128           # halo rows on either side of a knot block
 LANE_BUILD_MAX = 256  # curves up to this many knots are built by the first launch (tuning fused = 2)
+MIXED_WAVE_MAX = 512  # mixed precision: curves up to this many knots take the lane-parallel build
 GROUP_LANES = 16
 
 
@@ -32,23 +33,27 @@ def walk(koff, qoff, precision, tuning):
     ch = rows // 64
     # the first launch builds the curves of up to LANE_BUILD_MAX knots with
     # tuning fused = 2 (16 lanes per curve), every curve in mixed precision:
-    # those past LANE_BUILD_MAX knots one wavefront each with the sweeps on one
+    # those past MIXED_WAVE_MAX knots one wavefront each with the sweeps on one
     # lane (LDS arrays of MAX_N_BATCH rows), the others one wavefront each with
-    # the rows spread over its lanes (LDS arrays of 64 CH rows, CH <= 4)
+    # the rows spread over its lanes (LDS arrays of 64 CH rows, CH <= 8)
     mixed = precision == api.FP32_REFINE
     prebuilt = api.MAX_N_BATCH if mixed else LANE_BUILD_MAX if t.fused == 2 else 0
     assert sorted(lane.tolist()) == [i for i in range(count) if n[i] <= prebuilt]
     if len(lane):
         assert np.all(np.diff(n[lane]) <= 0), "first-launch curves are sorted by length"
-        grouped = n[lane][n[lane] <= LANE_BUILD_MAX]
         if mixed:
+            grouped = n[lane][n[lane] <= MIXED_WAVE_MAX]
             assert n[lane].max() <= api.MAX_N_BATCH
-            # the long ones lead the list: the one-wavefront launch takes
-            # slots 0 .. n_long - 1, the grouped launch the rest
-            n_long = int(np.count_nonzero(n[lane] > LANE_BUILD_MAX))
-            assert np.all(n[lane][:n_long] > LANE_BUILD_MAX) and np.all(n[lane][n_long:] <= LANE_BUILD_MAX)
+            # the long ones lead the list: the one-lane launch takes slots
+            # 0 .. n_long - 1, the lane-parallel launch the rest
+            n_long = int(np.count_nonzero(n[lane] > MIXED_WAVE_MAX))
+            assert np.all(n[lane][:n_long] > MIXED_WAVE_MAX) and np.all(n[lane][n_long:] <= MIXED_WAVE_MAX)
+        else:
+            grouped = n[lane][n[lane] <= LANE_BUILD_MAX]
         if len(grouped) and mixed:
-            assert grouped.max() <= 64 * -(-int(grouped.max()) // 64) <= 64 * 4  # the wavefront's LDS rows
+            ch = -(-int(grouped.max()) // 64)
+            ch = ch if ch <= 4 else 6 if ch <= 6 else 8  # the widths compiled
+            assert grouped.max() <= 64 * ch <= 64 * 8  # the wavefront's LDS rows
         elif len(grouped):
             lane_ch = 4 if grouped.max() <= GROUP_LANES * 4 else 9 if grouped.max() <= GROUP_LANES * 9 else 16
             assert grouped.max() <= GROUP_LANES * lane_ch  # the group's LDS rows (16 CH + 2)

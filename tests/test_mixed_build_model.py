@@ -194,7 +194,7 @@ BCS = [(1e32, 1e32), (0.0, 0.0), (-1.0, 1.0), (1e32, 0.5)]
 
 
 @pytest.mark.parametrize("G", [16, 64])
-@pytest.mark.parametrize("n", [3, 4, 5, 16, 17, 31, 33, 64, 65, 130, 144, 145, 200, 256])
+@pytest.mark.parametrize("n", [3, 4, 5, 16, 17, 31, 33, 64, 65, 130, 144, 145, 200, 256, 385, 512])
 @pytest.mark.parametrize("bc", BCS)
 def test_model_reaches_the_oracle(n, bc, G):
     x, y = w.paper_curve(np.random.default_rng(n), n)
@@ -225,11 +225,12 @@ def test_chunks_fit_the_group(G):
     G CH values) for every n it takes, CH the smallest width compiled for the
     group (4, 9, 16 for a row of 16; 1, 2, 3, 4 for a wavefront) that holds
     the batch; every row is owned by exactly one lane."""
-    for n in range(3, 257):
+    for n in range(3, 257 if G == 16 else 513):
         if G == 16:
             ch = 4 if n <= 64 else 9 if n <= 144 else 16
         else:
             ch = -(-n // 64)
+            ch = ch if ch <= 4 else 6 if ch <= 6 else 8
         r = -(-n // G)
         assert r <= ch and G * ch >= n
         owned = sorted(j for L in range(G) for j in range(L * r, min(n, L * r + r)))
