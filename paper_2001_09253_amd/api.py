@@ -237,7 +237,8 @@ def spline_plan_run_indexed(plan, bufs, idx, status=None, stream=None):
     """spline_plan_run that also writes every query's interval (within its
     curve) into idx (int32, sum m)."""
     _check(_native.lib().spline_plan_run_indexed(plan.handle, *_plan_args(plan, bufs),
-                                                 _dev(idx, torch.int32, "idx", int(plan.qoff[-1])),
+                                                 _dev(idx, torch.int32, "idx",
+                                                      0 if plan.qoff is None else int(plan.qoff[-1])),
                                                  _dev(status, torch.int32, "status", plan.count, optional=True),
                                                  _stream(stream)), "spline_plan_run_indexed")
 
