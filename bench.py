@@ -19,7 +19,8 @@ Workloads (--workload):
   small    1 curve, n = 13, m = 2048 (the worked size itself)
   plain2x  1 curve, n = 13,000, m = 2^27 (out of the 256 MB last-level cache)
   points   1 curve, n = 13,000, m = 2^27 explicit queries (random, or
-           --sorted), with first and second derivatives (spline_eval_points)
+           --sorted), with first and second derivatives: the curve's y''
+           built and packed, then spline_eval_points_packed
   batched_points
            the batched workload's 4096 curves, each at its own explicit
            points (as many as its uniform queries, uniform over its range,
@@ -421,10 +422,16 @@ def bench_points(args, sorted_queries):
     sd, ed = inst.start_deriv, inst.end_deriv
     K = args.steps
 
-    def build():  # y'' of the curve (the single-launch kernel, one throw-away query)
+    packed = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+
+    def build():  # y'' of the curve (the single-launch kernel, one throw-away query), then x, y, y'' interleaved
         api.spline_solve_uniform(x, y, sd, ed, 1, one, ypp, stream=sp)
+        api.spline_pack_knots(x, y, ypp, packed, stream=sp)
 
     def evaluate(derivs):
+        api.spline_eval_points_packed(packed, xq, yq, d1 if derivs else None, d2 if derivs else None, stream=sp)
+
+    def evaluate_unpacked(derivs):
         api.spline_eval_points(x, y, ypp, xq, yq, d1 if derivs else None, d2 if derivs else None, stream=sp)
 
     def timed(fn):
@@ -443,6 +450,8 @@ def bench_points(args, sorted_queries):
     build_ms, _ = timed(build)
     vals_ms, _ = timed(lambda: evaluate(False))
     eval_ms, _ = timed(lambda: evaluate(True))
+    unpacked_vals_ms, _ = timed(lambda: evaluate_unpacked(False))
+    unpacked_ms, _ = timed(lambda: evaluate_unpacked(True))
     step_ms, step_s = timed(lambda: (build(), evaluate(True)))
     # algorithmic bytes of the evaluation launch: read the points (8 per
     # query), write value, first and second derivative (24 per query), read
@@ -455,14 +464,15 @@ def bench_points(args, sorted_queries):
         "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "%s: 1 curve, n=13000, m=2^27 explicit points (%s), value + first and second "
-                               "derivative" % (wl, "sorted" if sorted_queries else "random order"),
+                               "derivative, from the packed curve" % (wl, "sorted" if sorted_queries else "random order"),
                    "instances": 1, "n": n, "m": m, "ends": "natural", "seed": 0,
                    "points": "U(x_0, x_{n-1}), numpy default_rng(1)"},
         "roofline": {"bound": "hbm", "kernel": "eval_points", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("eval_points", wl),
                      "algorithmic_bytes_per_launch": dbytes, "avg_launch_ms": eval_ms},
-        "kernels_ms": {"build": build_ms, "eval_points_values": vals_ms, "eval_points_with_derivatives": eval_ms,
-                       "step_event_ms": step_ms},
+        "kernels_ms": {"build_and_pack": build_ms, "eval_points_values": vals_ms,
+                       "eval_points_with_derivatives": eval_ms, "unpacked_values": unpacked_vals_ms,
+                       "unpacked_with_derivatives": unpacked_ms, "step_event_ms": step_ms},
         "values_only": {"ms": vals_ms, "frac": (16.0 * m + 24.0 * n) / (vals_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:

@@ -276,6 +276,24 @@ int spline_eval_points(const double *x, const double *y, const double *ypp, int6
                        const double *xq, int64_t m, double *yq, double *d1, double *d2,
                        int32_t *idx, void *stream);
 
+/* A curve's knots, values and second derivatives interleaved for explicit
+ * queries: packed[3j], packed[3j+1], packed[3j+2] = x[j], y[j], ypp[j] for
+ * j < n (packed: 3n device doubles, caller-owned).  An interval's six numbers
+ * then share one or two cache lines instead of three, which is what bounds
+ * explicit points in random order; pack once, evaluate many point sets.
+ * Asynchronous on `stream`; allocates nothing.  Errors: E_ARG (a pointer
+ * NULL), E_SIZE (n < 3), E_DEVICE. */
+int spline_pack_knots(const double *x, const double *y, const double *ypp, int64_t n, double *packed,
+                      void *stream);
+
+/* spline_eval_points on a packed curve (spline_pack_knots): the same kernel
+ * reading x, y and y'' from the n interleaved triples; the same intervals bit
+ * for bit, the same values and derivatives to rounding (the two compiled
+ * instantiations may contract a multiply and an add differently).  Errors: E_ARG
+ * (packed, xq or yq NULL), E_SIZE (n < 3 or m < 1), E_DEVICE. */
+int spline_eval_points_packed(const double *packed, int64_t n, const double *xq, int64_t m, double *yq,
+                              double *d1, double *d2, int32_t *idx, void *stream);
+
 /* Explicit queries over a batch, in one launch (the evaluation of "Fast
  * Interpolation" at any points, for many curves): count curves in CSR layout
  * on the device, koff and qoff (count + 1 int64 each, non-decreasing).  Curve

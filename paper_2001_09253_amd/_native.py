@@ -55,6 +55,8 @@ SIGNATURES = {
     "spline_noop_uniform": (C.c_int, [_vp, _i64, _i64, _vp, _vp]),
     "spline_eval_points": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "spline_batch_eval_points": (C.c_int, [_i64, _i64] + [_vp] * 11),
+    "spline_pack_knots": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "spline_eval_points_packed": (C.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "spline_plan_create": (C.c_int, [C.c_int, _i64, _vp, _vp, _u32, C.POINTER(Tuning), C.POINTER(_vp)]),
     "spline_plan_run": (C.c_int, [_vp] + [_vp] * 10),
     "spline_plan_run_indexed": (C.c_int, [_vp] + [_vp] * 11),

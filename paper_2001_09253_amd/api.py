@@ -166,6 +166,25 @@ def spline_eval_points(x, y, ypp, xq, yq, d1=None, d2=None, idx=None, stream=Non
            "spline_eval_points")
 
 
+def spline_pack_knots(x, y, ypp, packed, stream=None):
+    """Interleave x, y, y'' of one curve into packed (3 n device doubles)."""
+    n = x.numel()
+    _check(_native.lib().spline_pack_knots(_dev(x, name="x"), _dev(y, name="y", numel=n),
+                                           _dev(ypp, name="ypp", numel=n), n, _dev(packed, name="packed", numel=3 * n),
+                                           _stream(stream)), "spline_pack_knots")
+
+
+def spline_eval_points_packed(packed, xq, yq, d1=None, d2=None, idx=None, stream=None):
+    """spline_eval_points on a curve packed by spline_pack_knots."""
+    n, m = packed.numel() // 3, xq.numel()
+    _check(_native.lib().spline_eval_points_packed(_dev(packed, name="packed"), n, _dev(xq, name="xq"), m,
+                                                   _dev(yq, name="yq", numel=m),
+                                                   _dev(d1, name="d1", numel=m, optional=True),
+                                                   _dev(d2, name="d2", numel=m, optional=True),
+                                                   _dev(idx, torch.int32, "idx", m, optional=True), _stream(stream)),
+           "spline_eval_points_packed")
+
+
 def spline_batch_eval_points(koff, qoff, x, y, ypp, xq, yq, d1=None, d2=None, idx=None, stream=None):
     """Explicit points of many curves in one launch: koff, qoff device int64
     (count + 1, CSR), x, y, ypp per knot, xq and yq (and d1, d2, idx) per

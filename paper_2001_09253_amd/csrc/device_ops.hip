@@ -55,10 +55,8 @@ struct PointSmem {
     int32_t nan_any;
 };
 
-template <int BLOCK, int QPT, bool DERIVS, bool IDX>
-__global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __restrict__ x,
-                                                            const double* __restrict__ y,
-                                                            const double* __restrict__ ypp, int64_t n,
+template <int BLOCK, int QPT, bool DERIVS, bool IDX, typename K>
+__global__ __launch_bounds__(BLOCK) void eval_points_kernel(const K kn, int64_t n,
                                                             const double* __restrict__ xq, int64_t m,
                                                             double* __restrict__ yq, double* __restrict__ d1,
                                                             double* __restrict__ d2, int32_t* __restrict__ idx,
@@ -68,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
-    for (int f = tid; f < nf; f += BLOCK) sm.fence[f] = x[(int64_t)f * stride];
+    for (int f = tid; f < nf; f += BLOCK) sm.fence[f] = kn.X((int64_t)f * stride);
     __syncthreads();
     constexpr int64_t Q = (int64_t)BLOCK * QPT;
     for (int64_t k0 = (int64_t)blockIdx.x * Q; k0 < m; k0 += (int64_t)gridDim.x * Q) {
@@ -78,7 +76,7 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
 #pragma unroll
         for (int r = 0; r < QPT; ++r) {  // all loads of the tile first
             const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-            q[r] = k < m ? xq[k] : x[0];
+            q[r] = k < m ? xq[k] : kn.X(0);
         }
 #pragma unroll
         for (int r = 0; r < QPT; ++r) {
@@ -108,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
             // nan_any is cleared before the first of them)
             double v = sm.red[tid * NW];
             for (int w = 1; w < NW; ++w) v = tid == 0 ? fmin(v, sm.red[w]) : fmax(v, sm.red[NW + w]);
-            const int64_t iv = clip_interval(count_below_fenced(x, n, sm.fence, nf, stride, v), n);
+            const int64_t iv = clip_interval(count_below_fenced(kn, n, sm.fence, nf, stride, v), n);
             sm.win[tid] = (tid == 0 && sm.nan_any) ? -1 : iv;
         }
         __syncthreads();
@@ -118,9 +116,9 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
         if (staged) {
             const int W = (int)(ihi - ilo) + 2;
             for (int t = tid; t < W; t += BLOCK) {
-                sm.wx[t] = x[ilo + t];
-                sm.wy[t] = y[ilo + t];
-                sm.wp[t] = ypp[ilo + t];
+                sm.wx[t] = kn.X(ilo + t);
+                sm.wy[t] = kn.Y(ilo + t);
+                sm.wp[t] = kn.P(ilo + t);
             }
             __syncthreads();
 #pragma unroll
@@ -148,7 +146,7 @@ __global__ __launch_bounds__(BLOCK) void eval_points_kernel(const double* __rest
 #pragma unroll
             for (int r = 0; r < QPT; ++r) {
                 const int64_t k = k0 + (int64_t)r * BLOCK + tid;
-                if (k < m) eval_point<DERIVS, IDX>(x, y, ypp, n, sm.fence, nf, stride, q[r], k, yq, d1, d2, idx);
+                if (k < m) eval_point<DERIVS, IDX>(kn, n, sm.fence, nf, stride, q[r], k, yq, d1, d2, idx);
             }
         }
     }
@@ -200,9 +198,9 @@ int launch_eval_uniform_values(const double* x, const double* y, const double* y
     return launch_eval_uniform<kModeValue>(x, y, ypp, n, m, yq, s);
 }
 
-template <bool DERIVS, bool IDX>
-static int launch_points_t(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
-                           int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s) {
+template <bool DERIVS, bool IDX, typename K>
+static int launch_points_t(const K& kn, int64_t n, const double* xq, int64_t m, double* yq, double* d1, double* d2,
+                           int32_t* idx, hipStream_t s) {
     constexpr int QPT = 8;
     constexpr int64_t Q = (int64_t)kPointBlock * QPT;
     const int64_t stride = std::max<int64_t>(1, (n + kFenceMax - 1) / kFenceMax);
@@ -210,18 +208,47 @@ static int launch_points_t(const double* x, const double* y, const double* ypp, 
     const int64_t tiles = (m + Q - 1) / Q;
     // one round of resident workgroups
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count() * kPointGroups));
-    eval_points_kernel<kPointBlock, QPT, DERIVS, IDX><<<(unsigned)grid, kPointBlock, 0, s>>>(x, y, ypp, n, xq, m, yq,
-                                                                                             d1, d2, idx, stride, nf);
+    eval_points_kernel<kPointBlock, QPT, DERIVS, IDX, K><<<(unsigned)grid, kPointBlock, 0, s>>>(kn, n, xq, m, yq, d1, d2,
+                                                                                                idx, stride, nf);
     return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
+template <typename K>
+static int launch_points_any(const K& kn, int64_t n, const double* xq, int64_t m, double* yq, double* d1, double* d2,
+                             int32_t* idx, hipStream_t s) {
+    const bool derivs = d1 || d2;
+    if (derivs && idx) return launch_points_t<true, true>(kn, n, xq, m, yq, d1, d2, idx, s);
+    if (derivs) return launch_points_t<true, false>(kn, n, xq, m, yq, d1, d2, nullptr, s);
+    if (idx) return launch_points_t<false, true>(kn, n, xq, m, yq, nullptr, nullptr, idx, s);
+    return launch_points_t<false, false>(kn, n, xq, m, yq, nullptr, nullptr, nullptr, s);
 }
 
 int launch_eval_points(const double* x, const double* y, const double* ypp, int64_t n, const double* xq,
                        int64_t m, double* yq, double* d1, double* d2, int32_t* idx, hipStream_t s) {
-    const bool derivs = d1 || d2;
-    if (derivs && idx) return launch_points_t<true, true>(x, y, ypp, n, xq, m, yq, d1, d2, idx, s);
-    if (derivs) return launch_points_t<true, false>(x, y, ypp, n, xq, m, yq, d1, d2, nullptr, s);
-    if (idx) return launch_points_t<false, true>(x, y, ypp, n, xq, m, yq, nullptr, nullptr, idx, s);
-    return launch_points_t<false, false>(x, y, ypp, n, xq, m, yq, nullptr, nullptr, nullptr, s);
+    return launch_points_any(KnotsSoA{x, y, ypp}, n, xq, m, yq, d1, d2, idx, s);
+}
+
+// Interleave a curve's knots, values and second derivatives: t[3j], t[3j + 1],
+// t[3j + 2] = x_j, y_j, y''_j (coalesced reads, one pass).
+__global__ __launch_bounds__(256) void pack_knots_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                         const double* __restrict__ ypp, int64_t n,
+                                                         double* __restrict__ t) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        t[3 * j] = x[j];
+        t[3 * j + 1] = y[j];
+        t[3 * j + 2] = ypp[j];
+    }
+}
+
+int launch_pack_knots(const double* x, const double* y, const double* ypp, int64_t n, double* t, hipStream_t s) {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)device_cu_count() * 16));
+    pack_knots_kernel<<<(unsigned)blocks, 256, 0, s>>>(x, y, ypp, n, t);
+    return hipGetLastError() == hipSuccess ? SOLVE_OK : SOLVE_E_DEVICE;
+}
+
+int launch_eval_points_packed(const double* t, int64_t n, const double* xq, int64_t m, double* yq, double* d1,
+                              double* d2, int32_t* idx, hipStream_t s) {
+    return launch_points_any(KnotsPacked{t}, n, xq, m, yq, d1, d2, idx, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,8 +460,8 @@ __global__ __launch_bounds__(kBatchPtsBlock) void eval_points_batch_kernel(
                     put_point_lds<DERIVS, IDX>(sm.sx + b0, sm.sy + b0, sm.sp + b0, sm.sw + b0, (int)nc, qv, k, yq, d1,
                                                d2, idx);
                 else
-                    eval_point<DERIVS, IDX>(x + kbase, y + kbase, ypp + kbase, nc, sm.sx, nf, stride, qv, k, yq, d1,
-                                            d2, idx);
+                    eval_point<DERIVS, IDX>(KnotsSoA{x + kbase, y + kbase, ypp + kbase}, nc, sm.sx, nf, stride, qv,
+                                            k, yq, d1, d2, idx);
             }
             __syncthreads();  // (before the next window is staged)
             ca += nw;
@@ -527,4 +554,18 @@ extern "C" int spline_batch_eval_points(int64_t count, int64_t total_m, const in
     if (!koff || !qoff || !x || !y || !ypp || !xq || !yq) return SOLVE_E_ARG;
     if (count < 1 || total_m < 1) return SOLVE_E_SIZE;
     return launch_eval_points_batch(count, total_m, koff, qoff, x, y, ypp, xq, yq, d1, d2, idx, (hipStream_t)stream);
+}
+
+extern "C" int spline_pack_knots(const double* x, const double* y, const double* ypp, int64_t n, double* packed,
+                                 void* stream) {
+    if (!x || !y || !ypp || !packed) return SOLVE_E_ARG;
+    if (n < 3) return SOLVE_E_SIZE;
+    return launch_pack_knots(x, y, ypp, n, packed, (hipStream_t)stream);
+}
+
+extern "C" int spline_eval_points_packed(const double* packed, int64_t n, const double* xq, int64_t m, double* yq,
+                                         double* d1, double* d2, int32_t* idx, void* stream) {
+    if (!packed || !xq || !yq) return SOLVE_E_ARG;
+    if (n < 3 || m < 1) return SOLVE_E_SIZE;
+    return launch_eval_points_packed(packed, n, xq, m, yq, d1, d2, idx, (hipStream_t)stream);
 }

@@ -1409,6 +1409,31 @@ __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __
     eval_uniform_range<BLOCK, QPT, WIN, MODE, NT_STORE>(x, y, ypp, n, m, k0, k1, out, sm, tid);
 }
 
+// A curve's knots, values and second derivatives as the caller's three
+// arrays, or interleaved (knot j's x, y and y'' at t[3j], t[3j + 1],
+// t[3j + 2]: an interval's six numbers then share one or two cache lines,
+// where the three arrays put them on three).
+struct KnotsSoA {
+    const double* __restrict__ x;
+    const double* __restrict__ y;
+    const double* __restrict__ p;
+    __device__ __forceinline__ double X(int64_t j) const { return x[j]; }
+    __device__ __forceinline__ double Y(int64_t j) const { return y[j]; }
+    __device__ __forceinline__ double P(int64_t j) const { return p[j]; }
+};
+struct KnotsPacked {
+    const double* __restrict__ t;
+    __device__ __forceinline__ double X(int64_t j) const { return t[3 * j]; }
+    __device__ __forceinline__ double Y(int64_t j) const { return t[3 * j + 1]; }
+    __device__ __forceinline__ double P(int64_t j) const { return t[3 * j + 2]; }
+};
+// The knot positions of either layout, indexable for lower_bound_idx.
+template <typename K>
+struct KnotXs {
+    K k;
+    __device__ __forceinline__ double operator[](int64_t j) const { return k.X(j); }
+};
+
 // Explicit queries in any order (a5 by search, a6): the number of knots
 // below q is found in two steps.  A fence table in LDS holds every stride-th
 // knot, fence[f] = x[f * stride] for f < nf (nf = ceil(n / stride)); with c
@@ -1417,25 +1442,24 @@ __device__ void eval_uniform_tile(const double* __restrict__ x, const double* __
 // (at most stride - 1 of them, in global memory) completes the count.  The
 // interval is clip(count - 1, 0, n - 2), the definition itself; a NaN query
 // is below nothing and takes interval 0 (its value is NaN).
-__device__ __forceinline__ int64_t count_below_fenced(const double* __restrict__ x, int64_t n, const double* fence,
-                                                      int nf, int64_t stride, double q) {
+template <typename K>
+__device__ __forceinline__ int64_t count_below_fenced(const K& kn, int64_t n, const double* fence, int nf,
+                                                      int64_t stride, double q) {
     const int64_t c = lower_bound_idx(fence, 0, nf, q);  // fences below q
     if (c == 0) return 0;
     const int64_t lo = (c - 1) * stride + 1;
     const int64_t hi = min(c * stride, n);
-    return lower_bound_idx(x, lo, hi - lo, q);
+    return lower_bound_idx(KnotXs<K>{kn}, lo, hi - lo, q);
 }
 
-template <bool DERIVS, bool IDX>
-__device__ __forceinline__ void eval_point(const double* __restrict__ x, const double* __restrict__ y,
-                                           const double* __restrict__ ypp, int64_t n, const double* fence, int nf,
-                                           int64_t stride, double q, int64_t k, double* __restrict__ yq,
-                                           double* __restrict__ d1, double* __restrict__ d2,
-                                           int32_t* __restrict__ idx) {
-    const int64_t i = clip_interval(count_below_fenced(x, n, fence, nf, stride, q), n);
-    const double a = x[i], b = x[i + 1];
-    const double u = y[i], v = y[i + 1];
-    const double up = ypp[i], vp = ypp[i + 1];
+template <bool DERIVS, bool IDX, typename K>
+__device__ __forceinline__ void eval_point(const K& kn, int64_t n, const double* fence, int nf, int64_t stride,
+                                           double q, int64_t k, double* __restrict__ yq, double* __restrict__ d1,
+                                           double* __restrict__ d2, int32_t* __restrict__ idx) {
+    const int64_t i = clip_interval(count_below_fenced(kn, n, fence, nf, stride, q), n);
+    const double a = kn.X(i), b = kn.X(i + 1);
+    const double u = kn.Y(i), v = kn.Y(i + 1);
+    const double up = kn.P(i), vp = kn.P(i + 1);
     const double inv = 1.0 / (b - a);
     yq[k] = newint(q, a, b, u, v, up, vp, inv);
     if constexpr (DERIVS) {

@@ -73,6 +73,11 @@ def test_argument_errors_need_no_device(lib):
     assert lib.spline_noop_uniform(None, 5, 5, p, None) == api.E_ARG
     assert lib.spline_eval_points(p, p, p, 10, None, 5, p, None, None, None, None) == api.E_ARG
     assert lib.spline_batch_eval_points(5, 10, None, p, p, p, p, p, p, None, None, None, None) == api.E_ARG
+    assert lib.spline_pack_knots(p, None, p, 10, p, None) == api.E_ARG
+    assert lib.spline_pack_knots(p, p, p, 2, p, None) == api.E_SIZE
+    assert lib.spline_eval_points_packed(None, 10, p, 5, p, None, None, None, None) == api.E_ARG
+    assert lib.spline_eval_points_packed(p, 2, p, 5, p, None, None, None, None) == api.E_SIZE
+    assert lib.spline_eval_points_packed(p, 10, p, 0, p, None, None, None, None) == api.E_SIZE
     assert lib.spline_batch_eval_points(5, 10, p, p, p, p, p, p, None, None, None, None, None) == api.E_ARG
     assert lib.spline_batch_eval_points(0, 10, p, p, p, p, p, p, p, None, None, None, None) == api.E_SIZE
     assert lib.spline_batch_eval_points(5, 0, p, p, p, p, p, p, p, None, None, None, None) == api.E_SIZE
