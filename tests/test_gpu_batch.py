@@ -228,8 +228,9 @@ def test_batch_result_independent_of_company():
 # Mixed precision (FP32 sweeps, FP64 residual refinement of y'', FP32 cubic
 # term of the evaluation around the FP64 linear part).  Bounds, in the
 # per-instance scaled metric |g - o| / (|o| + max|o|):
-#   y'': two refinement steps take the FP32 solve error (~2^-24 times the
-#        system's conditioning per step) far below 1e-9;
+#   y'': one refinement step takes the FP32 solve error (~2^-24 times the
+#        conditioning of the diagonally dominant system) to its square,
+#        far below 1e-9 (the 4096-curve batch measures 2.1e-14 at most);
 #   y_q: the FP32 cubic term carries a few 2^-24 of its own size, which can
 #        exceed the values' scale by a small factor: 4e-6 (the 4096-curve
 #        batch measures 1.2e-6 at most, 1.4e-7 at the median).

@@ -12,7 +12,7 @@ shift by one lane, or lane shuffles for the suffix), and each lane then runs
 the paper's recurrences from its entering state (section on generating the second derivatives: the pivots
 c'_j, the forward substitution d'_j and the back substitution).  The FP64
 residual d - T y'' of the same rows, with the neighbouring lanes' y'' at the
-chunk ends, drives two refinement steps.  Here every step is taken in the
+chunk ends, drives the refinement (one step, as the kernel takes).  Here every step is taken in the
 kernel's order in numpy float32 / float64, so that a wrong scan direction, a
 dropped neighbour or an entering state taken from the wrong lane fails
 against the oracle's banded solve, in all four end conditions."""
@@ -22,7 +22,7 @@ import pytest
 import oracle
 from paper_2001_09253_amd import workloads as w
 
-REFINE = 2
+REFINE = 1
 F = np.float32
 
 
@@ -211,8 +211,9 @@ def test_fp32_solve_alone_is_an_fp32_solve(n, bc, G):
     """The FP32 solve before any refinement, on its own: within FP32 accuracy
     of the oracle (measured 6e-9 .. 1.3e-7), and not better than FP32 can be.
     This is what pins the scans: the refinement corrects a solver that is
-    merely a poor approximation (one that drops the cross-row broadcasts
-    still refines to 1e-13), while the solve alone is then off by 1e-3."""
+    merely a poor approximation (one that drops the cross-row broadcasts,
+    off by 1e-3 on its own), so a check of the refined result alone could
+    miss a broken scan."""
     x, y = w.paper_curve(np.random.default_rng(n), n)
     o = oracle.second_derivatives(x, y, *bc)
     err = np.abs(model_build(x, y, *bc, G=G, refine=0) - o).max() / np.abs(o).max()
